@@ -1,0 +1,172 @@
+"""Benchmark of the superlattice BTE time-stepping hot path on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--workload NAME] [--precision fp64|fp32]
+
+One "step" is a whole leap-frog step of the solver over the workload: the
+whole-grid half-step, the fractional-grid half-step and the per-step
+drift-velocity/absorption accumulation, as ``bte_step(1)`` queues it.  The
+default workload is the large low-temperature instance (512 harmonics x 8193
+phi_y points, mu = 10, E_dc = 4, E_w = 0.5, omega = 3, B = 6, dt = 2e-5),
+whose FP64 state (four planes, 134 MB per ping-pong set) is far larger than
+the L2 caches.  The state is resident in device memory before timing starts.
+
+Prints ONE JSON line.  ``value`` is grid-point updates per second
+(N_x * N_y * steps / s, whole steps, the paper's MLUPS convention x 1e6).
+``roofline`` compares the step kernel's algorithmic bytes per launch over its
+average launch duration (HIP events on the solver's stream) with the 8 TB/s
+HBM peak.  ``cpu_baseline`` times the FP64 CPU oracle on a bounded sample of
+the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, HERE)
+
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic bytes per cell and launch: the fused step reads and writes the
+# four state values of both grids once (8 values); a single half-step reads
+# its own two values and the other grid's two and writes two (6 values).
+VALUES_PER_CELL = {0: 8, 1: 6}   # kernel form -> state values moved per launch
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--workload", default="large_512x8193")
+    ap.add_argument("--precision", choices=("fp64", "fp32"), default="fp64")
+    ap.add_argument("--kernel", choices=("fused", "two_pass"), default="fused")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--cpu-sample-steps", type=int, default=0)
+    return ap.parse_args()
+
+
+def time_solver(bte, torch, w, precision, kernel, steps, warmup, tuning=None):
+    s = bte.Solver.from_workload(w, precision=precision)
+    if tuning:
+        s.set_tuning(**tuning)
+    s.set_tuning(kernel=kernel)
+    s.step(warmup)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    stream = s.stream
+    t0 = time.perf_counter()
+    start.record(stream)
+    s.step(steps)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = start.elapsed_time(stop)
+    obs = s.observables()
+    tune = s.tuning()
+    elem = 4 if precision == 1 else 8
+    launches_per_step = 1 if kernel == 0 else 2
+    bytes_per_launch = VALUES_PER_CELL[kernel] * elem * w.nx * w.ny
+    avg_launch_s = ms * 1e-3 / (steps * launches_per_step)
+    out = {
+        "ms": ms, "wall_s": wall, "steps": steps,
+        "cell_steps_per_s": w.nx * w.ny * steps / (ms * 1e-3),
+        "us_per_step": ms * 1e3 / steps,
+        "avg_launch_us": avg_launch_s * 1e6,
+        "bytes_per_launch": bytes_per_launch,
+        "achieved_GBs": bytes_per_launch / avg_launch_s / 1e9,
+        "status": int(obs.status), "v_dr": obs.v_dr, "norm": obs.norm,
+        "tuning": {"kernel": tune.kernel, "rows_per_wave": tune.rows_per_wave,
+                   "waves_per_block": tune.waves_per_block, "graph_steps": tune.graph_steps},
+    }
+    s.close()
+    return out
+
+
+def cpu_baseline(w, sample_steps):
+    import oracle
+    pb = oracle.Problem(nx=w.nx, ny=w.ny, phiy_min=w.phiy_min, phiy_max=w.phiy_max,
+                        E_dc=w.E_dc, E_w=w.E_w, omega=w.omega, B=w.B, mu=w.mu, dt=w.dt,
+                        alpha=w.alpha)
+    threads = oracle.max_threads()
+    if sample_steps <= 0:
+        # about 10-20 s of oracle work at ~2.5e7 cell-steps/s per thread
+        sample_steps = max(4, int(15 * 2.5e7 * threads / (w.nx * w.ny)))
+    oracle.run(pb, 1)                 # build/load, first touch
+    t0 = time.perf_counter()
+    oracle.run(pb, sample_steps)
+    secs = time.perf_counter() - t0
+    return {"value": w.nx * w.ny * sample_steps / secs, "unit": "grid-point updates/s",
+            "cores": threads, "kind": "oracle",
+            "sample": f"{w.name}: {sample_steps} whole steps from f0 (incl. start-up), "
+                      f"FP64, {secs:.1f} s, OpenMP threads={threads}"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the solver runs one instance per GPU, with no cross-GPU exchange).",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    from paper_1401_6047_amd import bte
+    from paper_1401_6047_amd import workloads as W
+
+    w = W.WORKLOADS[args.workload]
+    precision = 1 if args.precision == "fp32" else 0
+    kernel = 0 if args.kernel == "fused" else 1
+    main_run = time_solver(bte, torch, w, precision, kernel, args.steps, args.warmup)
+
+    variants = {}
+    if not args.no_variants:
+        other = 1 - precision
+        variants[f"{w.name}_{'fp32' if other else 'fp64'}"] = time_solver(
+            bte, torch, w, other, kernel, args.steps, args.warmup)
+        variants[f"{w.name}_{args.precision}_two_pass" if kernel == 0 else f"{w.name}_fused"] = \
+            time_solver(bte, torch, w, precision, 1 - kernel, args.steps, args.warmup)
+        c = W.CROSSED
+        variants[f"{c.name}_fp64"] = time_solver(bte, torch, c, 0, 0, 20000, 2000)
+        variants[f"{c.name}_fp32"] = time_solver(bte, torch, c, 1, 0, 20000, 2000)
+
+    ms = main_run["ms"]
+    line = {
+        "metric": "grid-point updates/s (N_x*N_y*steps/s) + % HBM peak",
+        "value": main_run["cell_steps_per_s"],
+        "unit": "grid-point updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if precision == 0 else "f32-storage/f64-compute",
+        "data": "synthetic (seeded parameters; state from the Boltzmann equilibrium)",
+        "config": {"workload": w.name, "n_x": w.nx, "n_y": w.ny, "dt": w.dt, "mu": w.mu,
+                   "E_dc": w.E_dc, "E_w": w.E_w, "omega": w.omega, "B": w.B,
+                   "precision": args.precision, "kernel": args.kernel,
+                   "tuning": main_run["tuning"]},
+        "roofline": {"bound": "hbm", "achieved": main_run["achieved_GBs"], "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": main_run["achieved_GBs"] / HBM_PEAK_GBS,
+                     "traffic": None,
+                     "kernel": "k_fused_step" if kernel == 0 else "k_half_step",
+                     "bytes_per_launch": main_run["bytes_per_launch"],
+                     "avg_launch_us": main_run["avg_launch_us"]},
+        "status": main_run["status"],
+    }
+    if variants:
+        line["variants"] = {k: {kk: v[kk] for kk in ("cell_steps_per_s", "us_per_step",
+                                                      "achieved_GBs", "avg_launch_us", "tuning")}
+                            for k, v in variants.items()}
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(w, args.cpu_sample_steps)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

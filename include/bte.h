@@ -1,0 +1,170 @@
+/*
+ * bte.h -- C ABI of the MI355X solver for the 2-D spatially homogeneous
+ * superlattice Boltzmann transport equation (D. Priimak, arXiv:1401.6047).
+ *
+ * The solver advances the Fourier-in-phi_x / finite-difference-in-phi_y
+ * distribution (a_n(phi_y), b_n(phi_y)) with the paper's combined
+ * Crank-Nicolson / staggered leap-frog scheme (Sec. 3: operator T, whole and
+ * fractional grids, start-up half-step) under E(t) = E_dc + E_w cos(w t) and
+ * constant B, relaxing towards the Boltzmann equilibrium (Sec. 2), and takes
+ * the drift-velocity and absorption reductions every step (Sec. 2, v_dr and
+ * A definitions).
+ *
+ * Conventions shared by every entry point:
+ *   - N_x harmonics are kept: a_0 .. a_{N_x-1} and b_1 .. b_{N_x-1}; b_0 is a
+ *     fixed zero.  phi_y(m) = phi_min + m (phi_max - phi_min)/(N_y - 1),
+ *     m = 0 .. N_y-1.  Both are zero outside these ranges (Sec. 3 boundary
+ *     conditions).
+ *   - Time is in units of the relaxation time tau (Sec. 2 scaling), so tau
+ *     must be 1.  The whole grid is at integer steps k (t = k dt), the
+ *     fractional grid at k + 1/2.
+ *   - Host arrays are row-major [n][m] doubles (m fastest), N_x * N_y long,
+ *     copied in or out before the call returns; the caller keeps ownership.
+ *   - Device memory is never allocated behind the caller's back when a
+ *     workspace is passed: the caller owns the workspace and keeps it alive
+ *     until bte_destroy.  Passing a NULL workspace makes the library allocate
+ *     (and free on destroy) one of the size bte_workspace_bytes reports.
+ *   - All device work is queued on the HIP stream given at creation (NULL =
+ *     the null stream).  bte_step only queues work; bte_observables,
+ *     bte_get_state and bte_set_state synchronise that stream.
+ *   - Every call returns a bte_status; no exception or abort crosses the ABI.
+ *     On failure bte_last_error() gives a message (thread-local, valid until
+ *     the next failing call on the same thread).
+ *   - A solver handle is not thread-safe; distinct handles are independent.
+ */
+#ifndef BTE_H
+#define BTE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    BTE_OK = 0,
+    BTE_EINVAL = -1,     /* invalid argument: nothing was changed */
+    BTE_ENOMEM = -2,     /* workspace too small, or allocation failed */
+    BTE_EDEVICE = -3,    /* a HIP runtime call failed */
+    BTE_EUNSTABLE = -4,  /* sticky: norm drifted or an observable is not finite */
+    BTE_ESTATE = -5      /* call not valid in the handle's current state */
+} bte_status;
+
+typedef enum {
+    BTE_FP64 = 0,        /* state and arithmetic in FP64 */
+    BTE_FP32_BULK = 1    /* state stored in FP32; cell update, scalars and
+                            accumulators in FP64 */
+} bte_precision;
+
+/* Kernel form used by bte_step. */
+typedef enum {
+    BTE_KERNEL_FUSED = 0,    /* one launch per step: whole + fractional half-steps
+                                fused, ping-pong state buffers */
+    BTE_KERNEL_TWO_PASS = 1  /* two launches per step, each half-step in place
+                                (the paper's two-kernel structure) */
+} bte_kernel;
+
+typedef struct {
+    int32_t n_x;         /* harmonics kept, >= 2 */
+    int32_t n_y;         /* phi_y points, both ends included, >= 3 */
+    double phiy_min;     /* box edges, phiy_max > phiy_min */
+    double phiy_max;
+} bte_grid;
+
+typedef struct {
+    double E_dc;         /* dc field (Sec. 2 field protocol) */
+    double E_w;          /* ac amplitude */
+    double omega;        /* ac angular frequency (> 0 when E_w != 0) */
+    double B;            /* magnetic field */
+    double mu;           /* Delta_1/(2 k_B T) > 0, sets f0 */
+    double alpha;        /* m/m_x > 0; enters the normalisation of f0 and v_dr only */
+    double tau;          /* must be 1: time is measured in units of tau */
+    double dt;           /* time step > 0, with dt |B| / (2 dphi) < 1 (leap-frog bound) */
+    int32_t precision;   /* bte_precision */
+    uint32_t flags;      /* reserved, must be 0 */
+} bte_params;
+
+/* Launch shape of the step kernels.  Zero fields take the library default
+   for the grid; bte_tune() picks them by measurement. */
+typedef struct {
+    int32_t kernel;          /* bte_kernel */
+    int32_t rows_per_wave;   /* harmonics handled by one wavefront, 1 .. 256 */
+    int32_t waves_per_block; /* 1, 2, 4 or 8 */
+    int32_t graph_steps;     /* steps per captured HIP graph (even), 0 = no graph */
+} bte_tuning;
+
+typedef struct {
+    int64_t step;        /* whole-grid step k of the current state */
+    double t;            /* k dt */
+    double v_dr;         /* pi sqrt(alpha) dphi sum_m b_1(m) at step k */
+    double norm;         /* 2 pi sqrt(alpha) dphi sum_m a_0(m) at step k */
+    int64_t n_avg;       /* steps accumulated in the current window */
+    double S_v;          /* sum of v_dr over the window */
+    double S_vc;         /* sum of v_dr cos(w t) over the window */
+    double v_avg;        /* S_v / n_avg (0 if n_avg = 0) */
+    double absorption;   /* (2 I_0(mu)/I_1(mu)) S_vc / n_avg  (Sec. 2 absorption) */
+    int32_t status;      /* BTE_OK or BTE_EUNSTABLE */
+    int32_t reserved;
+} bte_obs;
+
+typedef struct bte_solver bte_solver;
+
+/* Device bytes a solver with this grid and parameters needs.  Validates the
+   arguments the same way bte_create does. */
+bte_status bte_workspace_bytes(const bte_grid* grid, const bte_params* params, size_t* bytes);
+
+/* Create a solver: lay out the workspace, set the whole grid to the
+   equilibrium a_n = a^(0)_n, b_n = 0 (Sec. 2 initial condition) and compute
+   the fractional grid by the start-up half-step z^{1/2} = T(z^0) with time
+   step dt/2 (Sec. 3).  The step counter starts at 0 and the averaging window
+   is empty.  `workspace` is a device pointer of at least
+   bte_workspace_bytes() bytes (256-byte aligned) or NULL; `hip_stream` is a
+   hipStream_t or NULL. */
+bte_status bte_create(const bte_grid* grid, const bte_params* params, void* workspace,
+                      size_t workspace_bytes, void* hip_stream, bte_solver** out);
+
+/* Advance n_steps >= 0 whole steps (Sec. 3 leap-frog: whole grid k -> k+1
+   with coupling from the fractional grid, then fractional k+1/2 -> k+3/2
+   with coupling from the new whole grid).  Steps whose new index k+1 lies in
+   the averaging window add b_1(m) and b_1(m) cos(w (k+1) dt) to FP64
+   per-phi_y accumulators.  Queues work only. */
+bte_status bte_step(bte_solver* s, int64_t n_steps);
+
+/* Set the averaging window to steps k with lo < k <= hi and clear the
+   accumulators.  Steps already taken are not re-counted. */
+bte_status bte_set_window(bte_solver* s, int64_t lo, int64_t hi);
+
+/* Reduce and return the observables of the current state (synchronises). */
+bte_status bte_observables(bte_solver* s, bte_obs* out);
+
+/* Copy the state out as four [N_x][N_y] FP64 host arrays (whole grid a, b at
+   step k; fractional grid a, b at k + 1/2).  Any pointer may be NULL. */
+bte_status bte_get_state(bte_solver* s, double* a_h, double* b_h, double* a_f, double* b_f);
+
+/* Replace the state.  With a_f and b_f given, the four arrays become the
+   state at whole step `step` (a resume).  With a_f = b_f = NULL, (a_h, b_h)
+   becomes the state at step 0 and the fractional grid is recomputed by the
+   start-up half-step.  Row b[0] is ignored (b_0 is zero).  Clears the
+   accumulators and the unstable flag. */
+bte_status bte_set_state(bte_solver* s, const double* a_h, const double* b_h,
+                         const double* a_f, const double* b_f, int64_t step);
+
+/* Set or read the launch shape of the step kernels. */
+bte_status bte_set_tuning(bte_solver* s, const bte_tuning* t);
+bte_status bte_get_tuning(const bte_solver* s, bte_tuning* t);
+
+/* Destroy the handle; frees what the library allocated.  NULL is a no-op. */
+void bte_destroy(bte_solver* s);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* bte_last_error(void);
+
+/* Library version string. */
+const char* bte_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BTE_H */

@@ -1,0 +1,252 @@
+"""Thin Python binding of the C ABI in ``include/bte.h`` (ctypes).
+
+Argument marshalling only: every step of the solver runs in the HIP library
+``libbte.so``.  The library must have been built (``python -m
+paper_1401_6047_amd.build``); importing this module without it raises.
+PyTorch provides the device workspace and the stream.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbte.so")
+HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "bte.h")
+
+BTE_OK, BTE_EINVAL, BTE_ENOMEM, BTE_EDEVICE, BTE_EUNSTABLE, BTE_ESTATE = 0, -1, -2, -3, -4, -5
+BTE_FP64, BTE_FP32_BULK = 0, 1
+BTE_KERNEL_FUSED, BTE_KERNEL_TWO_PASS = 0, 1
+STATUS_NAMES = {0: "BTE_OK", -1: "BTE_EINVAL", -2: "BTE_ENOMEM", -3: "BTE_EDEVICE",
+                -4: "BTE_EUNSTABLE", -5: "BTE_ESTATE"}
+
+
+class bte_grid(ctypes.Structure):
+    _fields_ = [("n_x", ctypes.c_int32), ("n_y", ctypes.c_int32),
+                ("phiy_min", ctypes.c_double), ("phiy_max", ctypes.c_double)]
+
+
+class bte_params(ctypes.Structure):
+    _fields_ = [("E_dc", ctypes.c_double), ("E_w", ctypes.c_double),
+                ("omega", ctypes.c_double), ("B", ctypes.c_double),
+                ("mu", ctypes.c_double), ("alpha", ctypes.c_double),
+                ("tau", ctypes.c_double), ("dt", ctypes.c_double),
+                ("precision", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class bte_tuning(ctypes.Structure):
+    _fields_ = [("kernel", ctypes.c_int32), ("rows_per_wave", ctypes.c_int32),
+                ("waves_per_block", ctypes.c_int32), ("graph_steps", ctypes.c_int32)]
+
+
+class bte_obs(ctypes.Structure):
+    _fields_ = [("step", ctypes.c_int64), ("t", ctypes.c_double),
+                ("v_dr", ctypes.c_double), ("norm", ctypes.c_double),
+                ("n_avg", ctypes.c_int64), ("S_v", ctypes.c_double),
+                ("S_vc", ctypes.c_double), ("v_avg", ctypes.c_double),
+                ("absorption", ctypes.c_double), ("status", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class BteError(RuntimeError):
+    def __init__(self, status: int, func: str, msg: str):
+        super().__init__(f"{func}: {STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"HIP library {LIB_PATH} is not built; run "
+                          "`python -m paper_1401_6047_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    vp, dp = ctypes.c_void_p, P(ctypes.c_double)
+    sig = {
+        "bte_workspace_bytes": ([P(bte_grid), P(bte_params), P(ctypes.c_size_t)], ctypes.c_int),
+        "bte_create": ([P(bte_grid), P(bte_params), vp, ctypes.c_size_t, vp, P(vp)], ctypes.c_int),
+        "bte_step": ([vp, ctypes.c_int64], ctypes.c_int),
+        "bte_set_window": ([vp, ctypes.c_int64, ctypes.c_int64], ctypes.c_int),
+        "bte_observables": ([vp, P(bte_obs)], ctypes.c_int),
+        "bte_get_state": ([vp, dp, dp, dp, dp], ctypes.c_int),
+        "bte_set_state": ([vp, dp, dp, dp, dp, ctypes.c_int64], ctypes.c_int),
+        "bte_set_tuning": ([vp, P(bte_tuning)], ctypes.c_int),
+        "bte_get_tuning": ([vp, P(bte_tuning)], ctypes.c_int),
+        "bte_destroy": ([vp], None),
+        "bte_last_error": ([], ctypes.c_char_p),
+        "bte_version": ([], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    return lib
+
+
+_lib = _load()
+
+
+def header_functions(path: str = HEADER_PATH) -> list[str]:
+    """Names of the functions declared in include/bte.h."""
+    text = open(path).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(bte_[a-z_0-9]+)\s*\(", text)))
+
+
+def lib():
+    return _lib
+
+
+def _check(rc: int, func: str):
+    if rc != BTE_OK:
+        raise BteError(rc, func, _lib.bte_last_error().decode())
+
+
+def _dptr(a):
+    if a is None:
+        return None
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+# ---- the C entry points, same names --------------------------------------
+def bte_workspace_bytes(grid: bte_grid, params: bte_params) -> int:
+    n = ctypes.c_size_t(0)
+    _check(_lib.bte_workspace_bytes(ctypes.byref(grid), ctypes.byref(params), ctypes.byref(n)),
+           "bte_workspace_bytes")
+    return int(n.value)
+
+
+def bte_create(grid: bte_grid, params: bte_params, workspace_ptr: int, workspace_bytes: int,
+               stream_ptr: int) -> int:
+    h = ctypes.c_void_p(0)
+    _check(_lib.bte_create(ctypes.byref(grid), ctypes.byref(params),
+                           ctypes.c_void_p(workspace_ptr or None), workspace_bytes,
+                           ctypes.c_void_p(stream_ptr or None), ctypes.byref(h)), "bte_create")
+    return h.value
+
+
+def bte_step(h: int, n_steps: int):
+    _check(_lib.bte_step(ctypes.c_void_p(h), int(n_steps)), "bte_step")
+
+
+def bte_set_window(h: int, lo: int, hi: int):
+    _check(_lib.bte_set_window(ctypes.c_void_p(h), int(lo), int(hi)), "bte_set_window")
+
+
+def bte_observables(h: int) -> bte_obs:
+    o = bte_obs()
+    _check(_lib.bte_observables(ctypes.c_void_p(h), ctypes.byref(o)), "bte_observables")
+    return o
+
+
+def bte_get_state(h: int, a_h=None, b_h=None, a_f=None, b_f=None):
+    _check(_lib.bte_get_state(ctypes.c_void_p(h), _dptr(a_h), _dptr(b_h), _dptr(a_f), _dptr(b_f)),
+           "bte_get_state")
+
+
+def bte_set_state(h: int, a_h, b_h, a_f=None, b_f=None, step: int = 0):
+    _check(_lib.bte_set_state(ctypes.c_void_p(h), _dptr(a_h), _dptr(b_h), _dptr(a_f), _dptr(b_f),
+                              int(step)), "bte_set_state")
+
+
+def bte_set_tuning(h: int, t: bte_tuning):
+    _check(_lib.bte_set_tuning(ctypes.c_void_p(h), ctypes.byref(t)), "bte_set_tuning")
+
+
+def bte_get_tuning(h: int) -> bte_tuning:
+    t = bte_tuning()
+    _check(_lib.bte_get_tuning(ctypes.c_void_p(h), ctypes.byref(t)), "bte_get_tuning")
+    return t
+
+
+def bte_destroy(h: int):
+    _lib.bte_destroy(ctypes.c_void_p(h))
+
+
+def bte_last_error() -> str:
+    return _lib.bte_last_error().decode()
+
+
+def bte_version() -> str:
+    return _lib.bte_version().decode()
+
+
+# ---- convenience wrapper ---------------------------------------------------
+def make_grid(n_x, n_y, phiy_min, phiy_max) -> bte_grid:
+    return bte_grid(int(n_x), int(n_y), float(phiy_min), float(phiy_max))
+
+
+def make_params(E_dc, E_w, omega, B, mu, dt, alpha=1.0, tau=1.0, precision=BTE_FP64) -> bte_params:
+    return bte_params(float(E_dc), float(E_w), float(omega), float(B), float(mu), float(alpha),
+                      float(tau), float(dt), int(precision), 0)
+
+
+class Solver:
+    """One solver instance on the current torch device and stream.
+
+    The workspace is a torch uint8 tensor owned by this object; torch's
+    current stream is the stream every launch is queued on."""
+
+    def __init__(self, grid: bte_grid, params: bte_params, device="cuda", stream=None):
+        import torch
+        self.grid, self.params = grid, params
+        nbytes = bte_workspace_bytes(grid, params)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        base = self.workspace.data_ptr()
+        ptr = (base + 255) // 256 * 256
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        self.handle = bte_create(grid, params, ptr, nbytes, self.stream.cuda_stream)
+
+    @classmethod
+    def from_workload(cls, w, precision=BTE_FP64, **kw):
+        return cls(make_grid(w.nx, w.ny, w.phiy_min, w.phiy_max),
+                   make_params(w.E_dc, w.E_w, w.omega, w.B, w.mu, w.dt, alpha=w.alpha,
+                               precision=precision), **kw)
+
+    def step(self, n: int):
+        bte_step(self.handle, n)
+
+    def set_window(self, lo: int, hi: int):
+        bte_set_window(self.handle, lo, hi)
+
+    def observables(self) -> bte_obs:
+        return bte_observables(self.handle)
+
+    def state(self):
+        shape = (self.grid.n_x, self.grid.n_y)
+        arrs = [np.zeros(shape) for _ in range(4)]
+        bte_get_state(self.handle, *arrs)
+        return tuple(arrs)
+
+    def set_state(self, a_h, b_h, a_f=None, b_f=None, step=0):
+        c = lambda x: None if x is None else np.ascontiguousarray(x, dtype=np.float64)
+        bte_set_state(self.handle, c(a_h), c(b_h), c(a_f), c(b_f), step)
+
+    def tuning(self) -> bte_tuning:
+        return bte_get_tuning(self.handle)
+
+    def set_tuning(self, kernel=None, rows_per_wave=None, waves_per_block=None, graph_steps=None):
+        t = self.tuning()
+        if kernel is not None:
+            t.kernel = kernel
+        if rows_per_wave is not None:
+            t.rows_per_wave = rows_per_wave
+        if waves_per_block is not None:
+            t.waves_per_block = waves_per_block
+        if graph_steps is not None:
+            t.graph_steps = graph_steps
+        bte_set_tuning(self.handle, t)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            bte_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,95 @@
+// Internal declarations shared by the kernels and the host runtime of the
+// superlattice BTE solver.  Not part of the public C ABI (include/bte.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace bte {
+
+// Memory layout of one state plane (a_h, b_h, a_f or b_f):
+//   rows n = -kPadRows .. n_x - 1 + kPadRows, row stride `ld` elements,
+//   column m of the paper's phi_y lattice stored at physical column m + kPadCols.
+// Everything outside 0 <= n < n_x, 0 <= m < n_y is zero and never written, so
+// the stencil's boundary conditions (zero cells around the box) cost no branch.
+constexpr int kPadRows = 2;
+constexpr int kPadCols = 2;
+constexpr int kWave = 64;
+// Output columns of one wavefront: the fused step needs two halo lanes on each
+// side (whole-grid values are recomputed one column beyond the outputs), the
+// single half-step one.
+constexpr int kFusedCols = kWave - 4;
+constexpr int kHalfCols = kWave - 2;
+
+// Device-resident control block, read by every step kernel.  Keeping the step
+// counter on the device lets one captured graph be replayed for any k.
+struct Ctl {
+    int64_t k;        // whole step of the current state
+    int64_t win_lo;   // averaging window: win_lo < k+1 <= win_hi
+    int64_t win_hi;
+    int64_t pad;
+};
+
+// Per-solver scalars, fixed at creation.
+struct Consts {
+    int32_t nx, ny, ld;
+    int32_t pad;
+    double dt;        // time step
+    double half_dt;   // a half-step index j is the time j * half_dt
+    double phimin, dphi;
+    double B, E_dc, E_w, omega;
+    double c_full;    // B dt / (4 dphi): coupling coefficient of a full step
+    double nu, xi;    // 1 + dt/2, 1 - dt/2
+};
+
+template <typename T>
+struct Planes {
+    T* a_h;
+    T* b_h;
+    T* a_f;
+    T* b_f;
+};
+
+// Launch shapes (see bte_tuning in the public header).
+struct Shape {
+    int rows_per_wave;
+    int waves_per_block;
+};
+
+// ---- launchers (bte_kernels.hip) ------------------------------------------
+// All pointers to planes point at logical (n = 0, m = 0).
+
+// One fused leap-frog step: whole grid k -> k+1 from `src`, fractional grid
+// k+1/2 -> k+3/2, both written to `dst`.  The step index is ctl->k + j_off.
+template <typename T>
+hipError_t launch_fused_step(const Consts& cs, const Shape& sh, Planes<T> src, Planes<T> dst,
+                             const double* s_n, const double* g_m, double* acc_v,
+                             double* acc_vc, const Ctl* ctl, int j_off, hipStream_t st);
+
+// One half-step in place: X <- T(X; coupling from Y) with step h between
+// half-step times 2*(ctl->k + j_off) + off0 and 2*(ctl->k + j_off) + off1.
+// When `accumulate` is set the new b_1 row enters the window sums at step
+// ctl->k + j_off + 1.
+template <typename T>
+hipError_t launch_half_step(const Consts& cs, const Shape& sh, T* xa, T* xb, const T* ya,
+                            const T* yb, const double* s_n, const double* g_m, double h,
+                            int off0, int off1, int accumulate, double* acc_v, double* acc_vc,
+                            const Ctl* ctl, int j_off, hipStream_t st);
+
+// Fill the whole grid with the equilibrium a = s_n g_m, b = 0 (padding zero).
+template <typename T>
+hipError_t launch_init_equilibrium(const Consts& cs, T* a, T* b, const double* s_n,
+                                   const double* g_m, hipStream_t st);
+
+// ctl->k += n (one thread, vector store).
+hipError_t launch_advance_counter(Ctl* ctl, int64_t n, hipStream_t st);
+
+// Deterministic reduction: out[0] = sum_m a_h[0][m], out[1] = sum_m b_h[1][m],
+// out[2] = sum_m acc_v[m], out[3] = sum_m acc_vc[m].
+template <typename T>
+hipError_t launch_reduce_obs(const Consts& cs, const T* a_h, const T* b_h, const double* acc_v,
+                             const double* acc_vc, double* out, hipStream_t st);
+
+}  // namespace bte

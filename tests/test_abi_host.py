@@ -1,0 +1,80 @@
+"""Host-side checks of the C-ABI library: it loads, exports every symbol the
+header declares, and validates arguments (no GPU needed for any of this)."""
+import math
+import subprocess
+
+import pytest
+
+from paper_1401_6047_amd import bte
+
+
+def test_library_exports_every_header_symbol():
+    names = bte.header_functions()
+    assert {"bte_create", "bte_step", "bte_observables"} <= set(names)
+    for n in names:
+        assert hasattr(bte.lib(), n), n
+    out = subprocess.run(["nm", "-D", "--defined-only", bte.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = {line.split()[-1] for line in out.splitlines() if " T " in line}
+    missing = [n for n in names if n not in exported]
+    assert not missing, missing
+
+
+def test_version_and_last_error():
+    assert "gfx950" in bte.bte_version()
+    assert isinstance(bte.bte_last_error(), str)
+
+
+def _grid(**kw):
+    d = dict(n_x=128, n_y=1001, phiy_min=-10.0, phiy_max=10.0)
+    d.update(kw)
+    return bte.make_grid(**d)
+
+
+def _params(**kw):
+    d = dict(E_dc=6.0, E_w=0.1, omega=2.0, B=4.0, mu=1.0, dt=1e-4)
+    d.update(kw)
+    return bte.make_params(**d)
+
+
+def test_workspace_bytes_scales_with_grid_and_precision():
+    b64 = bte.bte_workspace_bytes(_grid(), _params())
+    b32 = bte.bte_workspace_bytes(_grid(), _params(precision=bte.BTE_FP32_BULK))
+    # 8 planes of (n_x + 4) x ld elements dominate
+    assert b64 > 8 * 132 * 1001 * 8
+    assert b32 < b64 and b32 > 8 * 132 * 1001 * 4
+    big = bte.bte_workspace_bytes(_grid(n_x=512, n_y=8193, phiy_min=-20, phiy_max=20),
+                                  _params(dt=2e-5, B=6.0))
+    assert big > 8 * 516 * 8193 * 8
+
+
+@pytest.mark.parametrize("grid_kw,param_kw,needle", [
+    (dict(n_x=1), {}, "n_x"),
+    (dict(n_y=2), {}, "n_y"),
+    (dict(phiy_min=1.0, phiy_max=1.0), {}, "phiy"),
+    (dict(phiy_max=math.inf), {}, "phiy"),
+    ({}, dict(dt=0.0), "dt"),
+    ({}, dict(mu=-1.0), "mu"),
+    ({}, dict(alpha=0.0), "alpha"),
+    ({}, dict(tau=2.0), "tau"),
+    ({}, dict(omega=0.0), "omega"),
+    ({}, dict(E_dc=math.nan), "finite"),
+    ({}, dict(precision=7), "precision"),
+    ({}, dict(B=4.0, dt=0.02), "leap-frog"),
+])
+def test_invalid_arguments_rejected(grid_kw, param_kw, needle):
+    with pytest.raises(bte.BteError) as ei:
+        bte.bte_workspace_bytes(_grid(**grid_kw), _params(**param_kw))
+    assert ei.value.status == bte.BTE_EINVAL
+    assert needle in str(ei.value)
+
+
+def test_omega_zero_allowed_without_ac_field():
+    assert bte.bte_workspace_bytes(_grid(), _params(E_w=0.0, omega=0.0)) > 0
+
+
+def test_flags_must_be_zero():
+    p = _params()
+    p.flags = 1
+    with pytest.raises(bte.BteError):
+        bte.bte_workspace_bytes(_grid(), p)

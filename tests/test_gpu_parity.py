@@ -1,0 +1,266 @@
+"""Parity of the HIP path with the FP64 CPU oracle (GPU tests).
+
+Every case runs the library through its C ABI (the ctypes binding) and the
+oracle on the same seeded inputs, and compares element by element: the four
+state planes and the observables.  Tolerances: FP64 state and observables to
+1e-10 relative (the bar for drift velocity and absorption; the state is held
+to a tighter 1e-12 of its maximum where runs are short), FP32-bulk to 1e-5.
+For absorption the relative error uses max(|A|, 1e-2 E_w) as denominator so
+that an A near zero does not turn rounding into a failure.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1401_6047_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.fixture(scope="module")
+def bte():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1401_6047_amd import bte as _bte      # raises if libbte.so is missing
+    return _bte
+
+
+def problem(w):
+    return oracle.Problem(nx=w.nx, ny=w.ny, phiy_min=w.phiy_min, phiy_max=w.phiy_max,
+                          E_dc=w.E_dc, E_w=w.E_w, omega=w.omega, B=w.B, mu=w.mu, dt=w.dt,
+                          alpha=w.alpha)
+
+
+def rel(x, ref, floor=0.0):
+    return abs(x - ref) / max(abs(ref), floor, 1e-300)
+
+
+def assert_state_close(got, ref, tol, what=""):
+    names = ("a_h", "b_h", "a_f", "b_f")
+    scale = max(np.abs(ref[0]).max(), np.abs(ref[1]).max(), 1e-300)
+    for g, r, n in zip(got, ref, names):
+        err = np.abs(g - r).max()
+        assert err <= tol * scale, f"{what} {n}: max err {err:.3e} > {tol:.1e} * {scale:.3e}"
+
+
+def run_gpu(bte, w, n_steps, window=(0, 0), precision=0, tuning=None, state=None):
+    s = bte.Solver.from_workload(w, precision=precision)
+    if tuning:
+        s.set_tuning(**tuning)
+    if state is not None:
+        s.set_state(*state)
+    if window != (0, 0):
+        s.set_window(*window)
+    s.step(n_steps)
+    o = s.observables()
+    st = s.state()
+    s.close()
+    return o, st
+
+
+def oracle_state(r):
+    return (r.a_h, r.b_h, r.a_f, r.b_f)
+
+
+# ---------------------------------------------------------------------------
+def test_esaki_tsu_closed_form(bte):
+    w = W.ESAKI_TSU
+    o, st = run_gpu(bte, w, w.n_steps)
+    assert o.status == 0 and o.step == 20000
+    assert abs(o.v_dr - 0.2231949831805269) <= 1e-12 * 0.2231949831805269
+    r = oracle.run(problem(w), w.n_steps)
+    assert rel(o.v_dr, r.v) < 1e-12
+    assert abs(o.norm - r.norm) < 1e-12
+    assert_state_close(st, oracle_state(r), 1e-12, "esaki-tsu")
+
+
+@pytest.fixture(scope="module")
+def crossed_ref():
+    w = W.CROSSED
+    return oracle.run(problem(w), 2000, window=(1000, 2000))
+
+
+TUNINGS = [
+    dict(kernel=0),
+    dict(kernel=0, rows_per_wave=1, waves_per_block=1, graph_steps=0),
+    dict(kernel=0, rows_per_wave=3, waves_per_block=2, graph_steps=8),
+    dict(kernel=0, rows_per_wave=7, waves_per_block=8, graph_steps=64),
+    dict(kernel=0, rows_per_wave=128, waves_per_block=4, graph_steps=2),
+    dict(kernel=1),
+    dict(kernel=1, rows_per_wave=5, waves_per_block=1, graph_steps=0),
+    dict(kernel=1, rows_per_wave=64, waves_per_block=8, graph_steps=16),
+]
+
+
+@pytest.mark.parametrize("tuning", TUNINGS, ids=lambda t: "-".join(f"{k}{v}" for k, v in t.items()))
+def test_crossed_fp64_matches_oracle(bte, crossed_ref, tuning):
+    w = W.CROSSED
+    o, st = run_gpu(bte, w, 2000, window=(1000, 2000), tuning=tuning)
+    r = crossed_ref
+    assert o.n_avg == r.K == 1000
+    assert rel(o.v_dr, r.v) < 1e-10
+    assert rel(o.norm, r.norm) < 1e-12
+    assert rel(o.v_avg, r.v_avg) < 1e-10
+    assert rel(o.absorption, r.absorption, 1e-2 * w.E_w) < 1e-10
+    assert_state_close(st, oracle_state(r), 1e-12, str(tuning))
+
+
+def test_crossed_fp32_bulk_matches_oracle(bte, crossed_ref):
+    w = W.CROSSED
+    o, st = run_gpu(bte, w, 2000, window=(1000, 2000), precision=bte.BTE_FP32_BULK)
+    r = crossed_ref
+    assert rel(o.v_dr, r.v) < 1e-5
+    assert rel(o.v_avg, r.v_avg) < 1e-5
+    assert rel(o.absorption, r.absorption, 1e-2 * w.E_w) < 1e-5
+    assert_state_close(st, oracle_state(r), 1e-5, "fp32")
+
+
+RAGGED = [(2, 3), (3, 5), (5, 61), (7, 65), (9, 119), (33, 121), (17, 187), (64, 250)]
+
+
+@pytest.mark.parametrize("nx,ny", RAGGED)
+@pytest.mark.parametrize("kernel", [0, 1])
+def test_ragged_grids_random_state(bte, nx, ny, kernel):
+    w = W.random_params(1000 + nx * 7 + ny, nx=nx, ny=ny, phi=6.0, dt=2e-3)
+    a, b = W.smooth_state(nx * 31 + ny, nx, ny, phi=6.0)
+    n = 150
+    o, st = run_gpu(bte, w, n, window=(40, 120), state=(a, b), tuning=dict(kernel=kernel))
+    r = oracle.run(problem(w), n, state=(a, b), window=(40, 120))
+    assert_state_close(st, oracle_state(r), 1e-12, f"{nx}x{ny}")
+    assert o.n_avg == r.K == 80
+    dphi = (w.phiy_max - w.phiy_min) / (w.ny - 1)
+    vscale = math.pi * dphi * np.abs(r.b_h[1]).sum() + 1e-300
+    assert abs(o.v_dr - r.v) < 1e-11 * vscale
+    assert abs(o.S_v - r.S_v) < 1e-11 * 80 * vscale
+    assert abs(o.S_vc - r.S_vc) < 1e-11 * 80 * vscale
+
+
+def test_zero_field_exact_relaxation(bte):
+    w = W.Workload("relax", nx=12, ny=61, phiy_min=-6, phiy_max=6, E_dc=0, E_w=0, omega=0, B=0,
+                   mu=1.5, dt=1e-2)
+    a, b = W.smooth_state(7, w.nx, w.ny, phi=6.0)
+    n = 300
+    _, st = run_gpu(bte, w, n, state=(a, b))
+    a0 = oracle.equilibrium(problem(w))
+    q = (1 - w.dt / 2) / (1 + w.dt / 2)
+    qh = (1 - w.dt / 4) / (1 + w.dt / 4)
+    b0 = b.copy(); b0[0] = 0
+    np.testing.assert_allclose(st[0], a0 + q ** n * (a - a0), rtol=0, atol=1e-14)
+    np.testing.assert_allclose(st[1], q ** n * b0, rtol=0, atol=1e-14)
+    np.testing.assert_allclose(st[2], a0 + q ** n * qh * (a - a0), rtol=0, atol=1e-14)
+
+
+def test_resume_is_bitwise_and_matches_oracle(bte):
+    w = W.random_params(77, nx=40, ny=333, phi=8.0, dt=1e-3)
+    s = bte.Solver.from_workload(w)
+    s.step(300)
+    mid = s.state()
+    s.step(200)
+    full = s.state()
+    o_full = s.observables()
+    s.close()
+    s2 = bte.Solver.from_workload(w)
+    s2.set_state(*mid, step=300)
+    s2.step(200)
+    again = s2.state()
+    o2 = s2.observables()
+    s2.close()
+    for x, y in zip(full, again):
+        np.testing.assert_array_equal(x, y)
+    assert o2.step == o_full.step == 500 and o2.v_dr == o_full.v_dr
+    r = oracle.run(problem(w), 500)
+    assert_state_close(full, oracle_state(r), 1e-12, "resume")
+
+
+def test_graph_and_direct_launches_agree_bitwise(bte):
+    w = W.random_params(5, nx=24, ny=200, dt=1e-3)
+    outs = []
+    for g in (0, 2, 32):
+        _, st = run_gpu(bte, w, 97, tuning=dict(graph_steps=g))
+        outs.append(st)
+    for st in outs[1:]:
+        for x, y in zip(outs[0], st):
+            np.testing.assert_array_equal(x, y)
+
+
+def test_window_set_mid_run(bte):
+    w = W.random_params(9, nx=16, ny=101, dt=2e-3)
+    s = bte.Solver.from_workload(w)
+    s.step(100)
+    s.set_window(120, 260)      # steps 121..260, starting to count from step 100
+    s.step(200)
+    o = s.observables()
+    s.close()
+    r = oracle.run(problem(w), 300, window=(120, 260))
+    assert o.n_avg == r.K == 140
+    assert rel(o.S_v, r.S_v) < 1e-11
+    assert rel(o.S_vc, r.S_vc, 1e-3 * abs(r.S_v)) < 1e-11
+
+
+def test_nan_state_flags_unstable(bte):
+    w = W.random_params(3, nx=8, ny=41, dt=2e-3)
+    s = bte.Solver.from_workload(w)
+    a, b, af, bf = s.state()
+    a[2, 20] = np.nan
+    s.set_state(a, b, af, bf, step=0)
+    s.step(5)
+    o = s.observables()
+    assert o.status == bte.BTE_EUNSTABLE
+    with pytest.raises(bte.BteError) as ei:
+        s.step(1)
+    assert ei.value.status == bte.BTE_EUNSTABLE
+    s.close()
+
+
+# ---------------------------------------------------------------------------
+# Full-length stored expectations written by tests/golden/make_golden.py.
+# ---------------------------------------------------------------------------
+def load_golden(name):
+    path = os.path.join(HERE, "golden", name)
+    if not os.path.exists(path):
+        pytest.skip(f"golden file {name} not generated")
+    with open(path) as f:
+        return json.load(f)
+
+
+def check_against_golden(o, st, g, w, tol_obs, tol_state):
+    ob = g["obs"]
+    assert o.step == g["n_steps"]
+    assert o.n_avg == ob["K"]
+    assert rel(o.v_dr, ob["v"]) < tol_obs
+    assert rel(o.v_avg, ob["v_avg"]) < tol_obs
+    assert rel(o.absorption, ob["absorption"], 1e-2 * w.E_w) < tol_obs
+    n = np.array(g["samples"]["n"]); m = np.array(g["samples"]["m"])
+    scale = g["maxabs"]["a_h"]
+    for i, key in enumerate(("a_h", "b_h", "a_f", "b_f")):
+        err = np.abs(st[i][n, m] - np.array(g["samples"][key])).max()
+        assert err <= tol_state * scale, (key, err)
+
+
+@pytest.mark.parametrize("precision,tol_obs,tol_state", [(0, 1e-10, 1e-11), (1, 1e-5, 1e-5)],
+                         ids=["fp64", "fp32bulk"])
+def test_crossed_full_length_vs_golden(bte, precision, tol_obs, tol_state):
+    g = load_golden("crossed_128x1001_full.json")
+    w = W.CROSSED
+    o, st = run_gpu(bte, w, w.n_steps, window=w.window, precision=precision)
+    print(f"crossed full precision={precision}: v_avg={o.v_avg!r} A={o.absorption!r} "
+          f"(oracle {g['obs']['v_avg']!r}, {g['obs']['absorption']!r})", flush=True)
+    check_against_golden(o, st, g, w, tol_obs, tol_state)
+
+
+@pytest.mark.parametrize("precision,tol_obs,tol_state", [(0, 1e-10, 1e-11), (1, 1e-5, 1e-5)],
+                         ids=["fp64", "fp32bulk"])
+def test_large_prefix_vs_golden(bte, precision, tol_obs, tol_state):
+    """512 x 8193 at full size, in the default launch configuration the
+    benchmark times, against the oracle's first 2000 steps."""
+    g = load_golden("large_512x8193_2000.json")
+    w = W.LARGE
+    o, st = run_gpu(bte, w, g["n_steps"], window=tuple(g["window"]), precision=precision)
+    check_against_golden(o, st, g, w, tol_obs, tol_state)
