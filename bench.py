@@ -47,14 +47,26 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=0)
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--rows-per-wave", type=int, default=0,
+                    help="fix the launch shape instead of autotuning (with --waves-per-block)")
+    ap.add_argument("--waves-per-block", type=int, default=0)
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="also run a plain device copy of this many MiB (counter calibration)")
     return ap.parse_args()
 
 
-def time_solver(bte, torch, w, precision, kernel, steps, warmup, tuning=None):
+def time_solver(bte, torch, w, precision, kernel, steps, warmup, autotune=True, shape=None):
     s = bte.Solver.from_workload(w, precision=precision)
-    if tuning:
-        s.set_tuning(**tuning)
-    s.set_tuning(kernel=kernel)
+    tuned_us = None
+    if shape:
+        s.set_tuning(kernel=kernel, rows_per_wave=shape[0], waves_per_block=shape[1])
+    elif autotune:
+        # outside the timed region: pick the launch shape by measurement, then
+        # keep the requested kernel form with the best shape found for it
+        _, tuned_us = s.autotune(kernel_form=kernel)
+    else:
+        s.set_tuning(kernel=kernel)
     s.step(warmup)
     torch.cuda.synchronize()
     start = torch.cuda.Event(enable_timing=True)
@@ -81,6 +93,7 @@ def time_solver(bte, torch, w, precision, kernel, steps, warmup, tuning=None):
         "bytes_per_launch": bytes_per_launch,
         "achieved_GBs": bytes_per_launch / avg_launch_s / 1e9,
         "status": int(obs.status), "v_dr": obs.v_dr, "norm": obs.norm,
+        "autotune_best_us_per_step": tuned_us,
         "tuning": {"kernel": tune.kernel, "rows_per_wave": tune.rows_per_wave,
                    "waves_per_block": tune.waves_per_block, "graph_steps": tune.graph_steps},
     }
@@ -124,18 +137,20 @@ def main():
     w = W.WORKLOADS[args.workload]
     precision = 1 if args.precision == "fp32" else 0
     kernel = 0 if args.kernel == "fused" else 1
-    main_run = time_solver(bte, torch, w, precision, kernel, args.steps, args.warmup)
+    at = not args.no_autotune
+    shape = (args.rows_per_wave, args.waves_per_block) if args.rows_per_wave > 0 else None
+    main_run = time_solver(bte, torch, w, precision, kernel, args.steps, args.warmup, at, shape)
 
     variants = {}
     if not args.no_variants:
         other = 1 - precision
         variants[f"{w.name}_{'fp32' if other else 'fp64'}"] = time_solver(
-            bte, torch, w, other, kernel, args.steps, args.warmup)
+            bte, torch, w, other, kernel, args.steps, args.warmup, at)
         variants[f"{w.name}_{args.precision}_two_pass" if kernel == 0 else f"{w.name}_fused"] = \
-            time_solver(bte, torch, w, precision, 1 - kernel, args.steps, args.warmup)
+            time_solver(bte, torch, w, precision, 1 - kernel, args.steps, args.warmup, at)
         c = W.CROSSED
-        variants[f"{c.name}_fp64"] = time_solver(bte, torch, c, 0, 0, 20000, 2000)
-        variants[f"{c.name}_fp32"] = time_solver(bte, torch, c, 1, 0, 20000, 2000)
+        variants[f"{c.name}_fp64"] = time_solver(bte, torch, c, 0, 0, 20000, 2000, at)
+        variants[f"{c.name}_fp32"] = time_solver(bte, torch, c, 1, 0, 20000, 2000, at)
 
     ms = main_run["ms"]
     line = {
@@ -163,6 +178,16 @@ def main():
         line["variants"] = {k: {kk: v[kk] for kk in ("cell_steps_per_s", "us_per_step",
                                                       "achieved_GBs", "avg_launch_us", "tuning")}
                             for k, v in variants.items()}
+    if args.copy_mib > 0:
+        # a plain device-to-device copy of known size, for scaling the HBM
+        # traffic counters of the step kernel
+        n = args.copy_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        line["copy_probe_mib"] = args.copy_mib
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_sample_steps)
     print(json.dumps(line), flush=True)

@@ -86,10 +86,10 @@ typedef struct {
 } bte_params;
 
 /* Launch shape of the step kernels.  Zero fields take the library default
-   for the grid; bte_tune() picks them by measurement. */
+   for the grid; bte_tune() picks one by measurement. */
 typedef struct {
     int32_t kernel;          /* bte_kernel */
-    int32_t rows_per_wave;   /* harmonics handled by one wavefront, 1 .. 256 */
+    int32_t rows_per_wave;   /* harmonics handled by one wavefront, 1 .. 62 */
     int32_t waves_per_block; /* 1, 2, 4 or 8 */
     int32_t graph_steps;     /* steps per captured HIP graph (even), 0 = no graph */
 } bte_tuning;
@@ -153,6 +153,19 @@ bte_status bte_set_state(bte_solver* s, const double* a_h, const double* b_h,
 /* Set or read the launch shape of the step kernels. */
 bte_status bte_set_tuning(bte_solver* s, const bte_tuning* t);
 bte_status bte_get_tuning(const bte_solver* s, bte_tuning* t);
+
+/* Autotuner: pick the launch shape by measurement.  Builds a scratch solver
+   for (grid, params) on `workspace` (bte_workspace_bytes of them; its contents
+   are overwritten), times each candidate shape -- kernel form (`kernel_form`
+   = a bte_kernel value, or -1 for both), 2..62 harmonics per wavefront, 1..8
+   wavefronts per block -- for about `target_ms` milliseconds (<= 0: 2 ms)
+   with HIP events on `hip_stream`, and writes the fastest to *best and its
+   time per step to *best_us_per_step (may be NULL).  The paper tunes its
+   kernels' block and grid sizes by hand (Sec. 7); this does it per grid.
+   Synchronises the stream. */
+bte_status bte_tune(const bte_grid* grid, const bte_params* params, void* workspace,
+                    size_t workspace_bytes, void* hip_stream, int32_t kernel_form,
+                    double target_ms, bte_tuning* best, double* best_us_per_step);
 
 /* Destroy the handle; frees what the library allocated.  NULL is a no-op. */
 void bte_destroy(bte_solver* s);

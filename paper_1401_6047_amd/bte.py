@@ -75,6 +75,8 @@ def _load():
         "bte_set_state": ([vp, dp, dp, dp, dp, ctypes.c_int64], ctypes.c_int),
         "bte_set_tuning": ([vp, P(bte_tuning)], ctypes.c_int),
         "bte_get_tuning": ([vp, P(bte_tuning)], ctypes.c_int),
+        "bte_tune": ([P(bte_grid), P(bte_params), vp, ctypes.c_size_t, vp, ctypes.c_int32,
+                      ctypes.c_double, P(bte_tuning), dp], ctypes.c_int),
         "bte_destroy": ([vp], None),
         "bte_last_error": ([], ctypes.c_char_p),
         "bte_version": ([], ctypes.c_char_p),
@@ -162,6 +164,17 @@ def bte_get_tuning(h: int) -> bte_tuning:
     return t
 
 
+def bte_tune(grid: bte_grid, params: bte_params, workspace_ptr: int, workspace_bytes: int,
+             stream_ptr: int, kernel_form: int = -1, target_ms: float = 2.0):
+    t = bte_tuning()
+    us = ctypes.c_double(0.0)
+    _check(_lib.bte_tune(ctypes.byref(grid), ctypes.byref(params),
+                         ctypes.c_void_p(workspace_ptr or None), workspace_bytes,
+                         ctypes.c_void_p(stream_ptr or None), int(kernel_form), float(target_ms),
+                         ctypes.byref(t), ctypes.byref(us)), "bte_tune")
+    return t, us.value
+
+
 def bte_destroy(h: int):
     _lib.bte_destroy(ctypes.c_void_p(h))
 
@@ -224,6 +237,20 @@ class Solver:
     def set_state(self, a_h, b_h, a_f=None, b_f=None, step=0):
         c = lambda x: None if x is None else np.ascontiguousarray(x, dtype=np.float64)
         bte_set_state(self.handle, c(a_h), c(b_h), c(a_f), c(b_f), step)
+
+    def autotune(self, kernel_form: int = -1, target_ms: float = 2.0):
+        """Pick the launch shape by measurement on a scratch copy of this
+        solver's grid (a separate workspace; this solver's state is untouched)
+        and apply it.  Returns (tuning, microseconds per step)."""
+        import torch
+        nbytes = bte_workspace_bytes(self.grid, self.params)
+        scratch = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.workspace.device)
+        ptr = (scratch.data_ptr() + 255) // 256 * 256
+        t, us = bte_tune(self.grid, self.params, ptr, nbytes, self.stream.cuda_stream,
+                         kernel_form, target_ms)
+        del scratch
+        bte_set_tuning(self.handle, t)
+        return t, us
 
     def tuning(self) -> bte_tuning:
         return bte_get_tuning(self.handle)

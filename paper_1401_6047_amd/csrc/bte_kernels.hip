@@ -26,14 +26,54 @@
 namespace bte {
 namespace {
 
-__device__ __forceinline__ double shfl_from_left(double v) { return __shfl_up(v, 1); }
-__device__ __forceinline__ double shfl_from_right(double v) { return __shfl_down(v, 1); }
+// ---- cross-lane moves --------------------------------------------------------
+// DPP wave shifts move a value one lane up or down the whole 64-lane wave in a
+// single VALU instruction per 32-bit half (no LDS round trip).  Lane l holds
+// phi_y column m, so "from left" is column m-1 and "from right" column m+1.
+// The two edge lanes receive garbage and are never used for output.
+constexpr int kDppWaveShr1 = 0x138;   // lane l <- lane l-1
+constexpr int kDppWaveShl1 = 0x130;   // lane l <- lane l+1
 
-template <typename T>
-__device__ __forceinline__ double ld_state(const T* p) { return static_cast<double>(*p); }
+__device__ __forceinline__ double dpp_move(double v, int ctrl_is_shr)
+{
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    int rlo, rhi;
+    if (ctrl_is_shr) {
+        rlo = __builtin_amdgcn_mov_dpp(lo, kDppWaveShr1, 0xF, 0xF, true);
+        rhi = __builtin_amdgcn_mov_dpp(hi, kDppWaveShr1, 0xF, 0xF, true);
+    } else {
+        rlo = __builtin_amdgcn_mov_dpp(lo, kDppWaveShl1, 0xF, 0xF, true);
+        rhi = __builtin_amdgcn_mov_dpp(hi, kDppWaveShl1, 0xF, 0xF, true);
+    }
+    return __hiloint2double(rhi, rlo);
+}
 
-template <typename T>
-__device__ __forceinline__ void st_state(T* p, double v) { *p = static_cast<T>(v); }
+// Centred difference across phi_y of a row held one column per lane:
+// v(m+1) - v(m-1).  The coupling terms A^t and B^t of Sec. 3 only ever use
+// the other grid through these differences, at harmonics n-1 and n+1.
+__device__ __forceinline__ double dphi_diff(double v)
+{
+    return dpp_move(v, 0) - dpp_move(v, 1);
+}
+
+// Broadcast lane `l` (wave-uniform) of a per-lane double to the whole wave.
+__device__ __forceinline__ double lane_bcast(double v, int l)
+{
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+    return __hiloint2double(hi, lo);
+}
+
+// 1/d for d >= 1: hardware reciprocal refined by two Newton steps (the error
+// is within a couple of ulp of the correctly rounded quotient).
+__device__ __forceinline__ double recip(double d)
+{
+    double x = __builtin_amdgcn_rcp(d);
+    double e = fma(-d, x, 1.0);
+    x = fma(x, e, x);
+    e = fma(-d, x, 1.0);
+    return fma(x, e, x);
+}
 
 // Operator T of Sec. 3 for one cell: Crank-Nicolson over a step h.
 //   g = a xi - b mu0 + B^t + a0 h,   h' = b xi + a mu0 + A^t,
@@ -44,7 +84,7 @@ __device__ __forceinline__ void op_T(double a, double b, double At, double Bt, d
 {
     const double g = fma(a, xi, fma(-b, mu0, Bt + a0h));
     const double hh = fma(b, xi, fma(a, mu0, At));
-    const double inv = 1.0 / fma(mu1, mu1, nu * nu);
+    const double inv = recip(fma(mu1, mu1, nu * nu));
     an = fma(g, nu, -hh * mu1) * inv;
     bn = fma(g, mu1, hh * nu) * inv;
 }
@@ -71,9 +111,61 @@ __device__ __forceinline__ int xcd_block()
     return (b & 7) * per + (b >> 3);
 }
 
+// Tile of this wavefront, made provably wave-uniform so that everything derived
+// from it (rows, loop bounds, row addresses) lives in scalar registers.
+__device__ __forceinline__ int wave_tile()
+{
+    const int t = xcd_block() * (blockDim.x / kWave) + (threadIdx.x / kWave);
+    return __builtin_amdgcn_readfirstlane(t);
+}
+
+// Row access through a buffer resource: the row offset is a scalar (SGPR)
+// operand and the lane's column a 32-bit VGPR offset, so no vector address
+// arithmetic is spent per access.  The descriptor's record count is the
+// plane's size: an access outside the plane reads 0 and a store is dropped.
+constexpr int kBufferWord3 = 0x00020000;   // gfx9 raw buffer, no format conversion
+
+template <typename T>
+struct RowAddr {
+    __amdgpu_buffer_rsrc_t rsrc;
+    uint32_t row_bytes;   // ld * sizeof(T)
+    uint32_t col_bytes;   // (m + kPadCols) * sizeof(T), per lane
+    __device__ __forceinline__ RowAddr(const T* base, uint32_t plane_bytes, uint32_t rb, uint32_t cb)
+        : rsrc(__builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(base), static_cast<short>(0),
+                                                 static_cast<int>(plane_bytes), kBufferWord3)),
+          row_bytes(rb), col_bytes(cb)
+    {
+    }
+    __device__ __forceinline__ int soff(int j) const
+    {
+        return static_cast<int>(static_cast<uint32_t>(j + kPadRows) * row_bytes);
+    }
+    __device__ __forceinline__ double load(int j) const
+    {
+        if constexpr (sizeof(T) == 8) {
+            auto v = __builtin_amdgcn_raw_buffer_load_b64(rsrc, col_bytes, soff(j), 0);
+            return __builtin_bit_cast(double, v);
+        } else {
+            auto v = __builtin_amdgcn_raw_buffer_load_b32(rsrc, col_bytes, soff(j), 0);
+            return static_cast<double>(__builtin_bit_cast(float, v));
+        }
+    }
+    __device__ __forceinline__ void store(int j, double x) const
+    {
+        if constexpr (sizeof(T) == 8) {
+            using V = decltype(__builtin_amdgcn_raw_buffer_load_b64(rsrc, 0u, 0, 0));
+            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, x), rsrc, col_bytes, soff(j), 0);
+        } else {
+            using V = decltype(__builtin_amdgcn_raw_buffer_load_b32(rsrc, 0u, 0, 0));
+            const float f = static_cast<float>(x);
+            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(V, f), rsrc, col_bytes, soff(j), 0);
+        }
+    }
+};
+
 template <typename T>
 struct FusedArgs {
-    Planes<T> src;
+    Planes<T> src;     // physical plane bases (row -kPadRows, column -kPadCols)
     Planes<T> dst;
     const double* s_n;
     const double* g_m;
@@ -87,12 +179,21 @@ struct FusedArgs {
     int ntiles;   // nchunks * ceil(ny / kFusedCols)
 };
 
+// Registers of one slot of the sliding window (see k_fused_step).
+struct RowRegs {
+    double fa, fb;     // old fractional grid, own column
+    double dfa, dfb;   // its phi_y differences
+    double dha, dhb;   // phi_y differences of the new whole grid (row r or r-3)
+    double nfa, nfb;   // in flight: inputs of the iteration that next uses this
+    double nha, nhb;   //   slot as its centre row (old fractional row j+1, old whole row j)
+};
+
 template <typename T>
-__global__ __launch_bounds__(512) void k_fused_step(FusedArgs<T> A)
+__global__ __launch_bounds__(512) void k_fused_step(FusedArgs<T> A, const double* __restrict__ s_n)
 {
     const Consts& cs = A.cs;
     const int lane = threadIdx.x & (kWave - 1);
-    const int tile = xcd_block() * (blockDim.x / kWave) + (threadIdx.x / kWave);
+    const int tile = wave_tile();
     if (tile >= A.ntiles) return;                    // wave-uniform
     const int ct = tile / A.nchunks;
     const int r0 = (tile - ct * A.nchunks) * A.R;
@@ -108,98 +209,130 @@ __global__ __launch_bounds__(512) void k_fused_step(FusedArgs<T> A)
     const bool acc_step = (k + 1 > ctl.win_lo) && (k + 1 <= ctl.win_hi);
 
     const double phi = fma(static_cast<double>(m), cs.dphi, cs.phimin);
-    const double gm = col_ok ? A.g_m[m] : 0.0;
+    const double gdt = (col_ok ? A.g_m[m] : 0.0) * cs.dt;
+    // s_n of harmonics r0-1 .. r1 (at most 64 of them), one per lane; row j's
+    // value is broadcast from lane j - (r0 - 1).
+    const double s_lane = s_n[min(max(r0 - 1 + lane, 0), cs.nx - 1)];
     const double hdt = 0.5 * cs.dt;
     // mu^t = n beta^t dt/2 with beta^t = E(t) + B phi: per-lane factor q, mu = n q.
     const double q0h = (fma(cs.E_w, cw[0], cs.E_dc) + cs.B * phi) * hdt;  // t = k dt
     const double q1h = (fma(cs.E_w, cw[2], cs.E_dc) + cs.B * phi) * hdt;  // t = (k+1) dt
     const double q0f = (fma(cs.E_w, cw[1], cs.E_dc) + cs.B * phi) * hdt;  // (k+1/2) dt
     const double q1f = (fma(cs.E_w, cw[3], cs.E_dc) + cs.B * phi) * hdt;  // (k+3/2) dt
-    const double c = cs.c_full, nu = cs.nu, xi = cs.xi, dt = cs.dt;
+    const double c = cs.c_full, nu = cs.nu, xi = cs.xi;
 
-    const int ld = cs.ld;
-    const T* __restrict__ aHs = A.src.a_h + m;
-    const T* __restrict__ bHs = A.src.b_h + m;
-    const T* __restrict__ aFs = A.src.a_f + m;
-    const T* __restrict__ bFs = A.src.b_f + m;
-    T* __restrict__ aHd = A.dst.a_h + m;
-    T* __restrict__ bHd = A.dst.b_h + m;
-    T* __restrict__ aFd = A.dst.a_f + m;
-    T* __restrict__ bFd = A.dst.b_f + m;
+    const uint32_t rb = static_cast<uint32_t>(cs.ld) * sizeof(T);
+    const uint32_t cb = static_cast<uint32_t>(m + kPadCols) * sizeof(T);
+    const uint32_t pb = static_cast<uint32_t>(cs.nx + 2 * kPadRows) * rb;
+    const RowAddr<T> aHs(A.src.a_h, pb, rb, cb);
+    const RowAddr<T> bHs(A.src.b_h, pb, rb, cb);
+    const RowAddr<T> aFs(A.src.a_f, pb, rb, cb);
+    const RowAddr<T> bFs(A.src.b_f, pb, rb, cb);
+    const RowAddr<T> aHd(A.dst.a_h, pb, rb, cb);
+    const RowAddr<T> bHd(A.dst.b_h, pb, rb, cb);
+    const RowAddr<T> aFd(A.dst.a_f, pb, rb, cb);
+    const RowAddr<T> bFd(A.dst.b_f, pb, rb, cb);
 
-    // Old fractional grid, own column, rows j-1 (0), j (1), j+1 (2); and its
-    // left/right neighbours for rows j-1 and j+1.
-    double fa0 = ld_state(aFs + (r0 - 2) * ld), fb0 = ld_state(bFs + (r0 - 2) * ld);
-    double fa1 = ld_state(aFs + (r0 - 1) * ld), fb1 = ld_state(bFs + (r0 - 1) * ld);
-    double fal0 = shfl_from_left(fa0), far0 = shfl_from_right(fa0);
-    double fbl0 = shfl_from_left(fb0), fbr0 = shfl_from_right(fb0);
-    double fal1 = shfl_from_left(fa1), far1 = shfl_from_right(fa1);
-    double fbl1 = shfl_from_left(fb1), fbr1 = shfl_from_right(fb1);
-    // New whole grid, neighbours only, rows j-2 (0), j-1 (1).
-    double hal0 = 0, har0 = 0, hbl0 = 0, hbr0 = 0;
-    double hal1 = 0, har1 = 0, hbl1 = 0, hbr1 = 0;
+    // Sliding window over harmonics.  Iteration j computes the new whole grid
+    // at harmonic j (needs old fractional rows j-1, j+1) and the new
+    // fractional grid at harmonic j-1 (needs new whole rows j-2, j).  Row r's
+    // registers live in slot r mod 3; the slot of row j+1 still holds the new
+    // whole-grid differences of row j-2 when iteration j reads them.
+    RowRegs S[3];
+    S[0] = S[1] = S[2] = RowRegs{0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    const int jlo = r0 - 1;
+    // Loads run three iterations ahead: iteration j consumes old fractional
+    // row j+1 and old whole row j from the slot of row j and refills that slot
+    // with the inputs of iteration j+3.  Clamped rows stay inside the plane;
+    // the values loaded for iterations past the end are never used.
+    auto issue = [&](RowRegs& P, int j) {
+        const int jf = min(j + 1, r1 + 1);
+        const int jh = min(j, r1);
+        P.nfa = aFs.load(jf);
+        P.nfb = bFs.load(jf);
+        P.nha = aHs.load(jh);
+        P.nhb = bHs.load(jh);
+    };
+    // prime: old fractional rows r0-2 (slot of jlo-1) and r0-1 (slot of jlo)
+    {
+        RowRegs& a = S[0];
+        a.fa = aFs.load(r0 - 2);
+        a.fb = bFs.load(r0 - 2);
+        RowRegs& b = S[1];
+        b.fa = aFs.load(r0 - 1);
+        b.fb = bFs.load(r0 - 1);
+        issue(S[1], jlo);
+        issue(S[2], jlo + 1);
+        issue(S[0], jlo + 2);
+        a.dfa = dphi_diff(a.fa);
+        a.dfb = dphi_diff(a.fb);
+        b.dfa = dphi_diff(b.fa);
+        b.dfb = dphi_diff(b.fb);
+    }
 
-    for (int j = r0 - 1; j <= r1; ++j) {
-        const double fa2 = ld_state(aFs + (j + 1) * ld);
-        const double fb2 = ld_state(bFs + (j + 1) * ld);
-        const double fal2 = shfl_from_left(fa2), far2 = shfl_from_right(fa2);
-        const double fbl2 = shfl_from_left(fb2), fbr2 = shfl_from_right(fb2);
+    auto iter = [&](int j, RowRegs& Pm, RowRegs& P0, RowRegs& Pp) {
+        // old fractional row j+1 and old whole row j, loaded three iterations ago
+        Pp.fa = P0.nfa;
+        Pp.fb = P0.nfb;
+        const double ha_old = P0.nha, hb_old = P0.nhb;
+        issue(P0, j + 3);
+        Pp.dfa = dphi_diff(Pp.fa);
+        Pp.dfb = dphi_diff(Pp.fb);
 
         // ---- whole grid, harmonic j: z^{k+1} = T(z^k; A, B from z^{k+1/2})
-        const double nd = static_cast<double>(j);
-        const int nc = min(max(j, 0), cs.nx - 1);
-        const double s = A.s_n[nc];
+        const double sdt = lane_bcast(s_lane, min(j - (r0 - 1), kWave - 1)) * gdt;
         const double chi = (j == 1) ? 2.0 : 1.0;
+        const double nd = static_cast<double>(j);
         double ha, hb;
-        {
-            const double a = ld_state(aHs + j * ld);
-            const double b = ld_state(bHs + j * ld);
-            const double At = c * (chi * (far0 - fal0) - far2 + fal2);
-            const double Bt = c * ((fbr2 - fbl2) - fbr0 + fbl0);
-            op_T(a, b, At, Bt, s * gm * dt, nd * q0h, nd * q1h, nu, xi, ha, hb);
-        }
+        op_T(ha_old, hb_old, c * (chi * Pm.dfa - Pp.dfa), c * (Pp.dfb - Pm.dfb), sdt, nd * q0h,
+             nd * q1h, nu, xi, ha, hb);
         const bool row_a = (j >= 0) && (j < cs.nx) && col_ok;
-        const bool row_b = row_a && (j >= 1);
         ha = row_a ? ha : 0.0;
-        hb = row_b ? hb : 0.0;
-        if (out_lane && j >= r0 && j < r1) {
-            st_state(aHd + j * ld, ha);
-            st_state(bHd + j * ld, hb);
-            if (j == 1 && acc_step) {                // drift-velocity window sums
-                A.acc_v[m] += hb;
-                A.acc_vc[m] += hb * cw[2];
+        hb = (row_a && j >= 1) ? hb : 0.0;
+        if (j >= r0 && j < r1) {
+            if (out_lane) {
+                aHd.store(j, ha);
+                bHd.store(j, hb);
+                if (j == 1 && acc_step) {            // drift-velocity window sums
+                    A.acc_v[m] += hb;
+                    A.acc_vc[m] += hb * cw[2];
+                }
             }
         }
-        const double hal2 = shfl_from_left(ha), har2 = shfl_from_right(ha);
-        const double hbl2 = shfl_from_left(hb), hbr2 = shfl_from_right(hb);
+        P0.dha = dphi_diff(ha);
+        P0.dhb = dphi_diff(hb);
 
         // ---- fractional grid, harmonic j-1: z^{k+3/2} = T(z^{k+1/2}; A, B from z^{k+1})
         const int n = j - 1;
-        if (n >= r0) {
-            const double nd1 = static_cast<double>(n);
-            const double s1 = A.s_n[min(max(n, 0), cs.nx - 1)];
+        if (n >= r0 && n < r1) {
+            const double sdt1 = lane_bcast(s_lane, n - (r0 - 1)) * gdt;
             const double chi1 = (n == 1) ? 2.0 : 1.0;
-            const double At = c * (chi1 * (har0 - hal0) - har2 + hal2);
-            const double Bt = c * ((hbr2 - hbl2) - hbr0 + hbl0);
+            const double nd1 = static_cast<double>(n);
             double fa, fb;
-            op_T(fa0, fb0, At, Bt, s1 * gm * dt, nd1 * q0f, nd1 * q1f, nu, xi, fa, fb);
+            // new whole rows n-1 = j-2 (held in the slot of j+1) and n+1 = j
+            op_T(Pm.fa, Pm.fb, c * (chi1 * Pp.dha - P0.dha), c * (P0.dhb - Pp.dhb), sdt1,
+                 nd1 * q0f, nd1 * q1f, nu, xi, fa, fb);
             if (out_lane) {
-                st_state(aFd + n * ld, fa);
-                st_state(bFd + n * ld, n >= 1 ? fb : 0.0);
+                aFd.store(n, fa);
+                bFd.store(n, n >= 1 ? fb : 0.0);
             }
         }
-        // rotate the register window
-        fa0 = fa1; fb0 = fb1; fa1 = fa2; fb1 = fb2;
-        fal0 = fal1; far0 = far1; fbl0 = fbl1; fbr0 = fbr1;
-        fal1 = fal2; far1 = far2; fbl1 = fbl2; fbr1 = fbr2;
-        hal0 = hal1; har0 = har1; hbl0 = hbl1; hbr0 = hbr1;
-        hal1 = hal2; har1 = har2; hbl1 = hbl2; hbr1 = hbr2;
+    };
+
+    // R + 2 iterations, padded to a multiple of 3 so that the loop body is
+    // exactly periodic in the slot rotation (no register copies of loads in
+    // flight at the back edge); padding iterations store nothing.
+    const int jend = jlo + (r1 - jlo + 1 + 2) / 3 * 3;
+    for (int j = jlo; j < jend; j += 3) {
+        iter(j, S[0], S[1], S[2]);
+        iter(j + 1, S[1], S[2], S[0]);
+        iter(j + 2, S[2], S[0], S[1]);
     }
 }
 
 template <typename T>
 struct HalfArgs {
-    T* xa;
+    T* xa;          // physical plane bases
     T* xb;
     const T* ya;
     const T* yb;
@@ -221,11 +354,11 @@ struct HalfArgs {
 // One half-step of the paper's two-kernel structure, in place on X (a cell of
 // X reads only its own old value; all neighbour reads hit Y).
 template <typename T>
-__global__ __launch_bounds__(512) void k_half_step(HalfArgs<T> A)
+__global__ __launch_bounds__(512) void k_half_step(HalfArgs<T> A, const double* __restrict__ s_n)
 {
     const Consts& cs = A.cs;
     const int lane = threadIdx.x & (kWave - 1);
-    const int tile = xcd_block() * (blockDim.x / kWave) + (threadIdx.x / kWave);
+    const int tile = wave_tile();
     if (tile >= A.ntiles) return;
     const int ct = tile / A.nchunks;
     const int r0 = (tile - ct * A.nchunks) * A.R;
@@ -241,51 +374,57 @@ __global__ __launch_bounds__(512) void k_half_step(HalfArgs<T> A)
     const double cv = cos(cs.omega * tt);
     const double c0 = __shfl(cv, 0), c1 = __shfl(cv, 1);
     const bool acc_step = A.accumulate && (k + 1 > ctl.win_lo) && (k + 1 <= ctl.win_hi);
-    const double cw_acc = cos(cs.omega * static_cast<double>(2 * k + 2) * cs.half_dt);
+    const double cw_acc = acc_step ? cos(cs.omega * static_cast<double>(2 * k + 2) * cs.half_dt) : 0.0;
 
     const double h = A.h;
     const double nu = 1.0 + 0.5 * h, xi = 1.0 - 0.5 * h;
     const double c = cs.B * h / (4.0 * cs.dphi);
     const double phi = fma(static_cast<double>(m), cs.dphi, cs.phimin);
-    const double gm = col_ok ? A.g_m[m] : 0.0;
+    const double gh = (col_ok ? A.g_m[m] : 0.0) * h;
+    const double s_lane = s_n[min(r0 + lane, cs.nx - 1)];   // harmonics r0 .. r1-1
     const double q0 = (fma(cs.E_w, c0, cs.E_dc) + cs.B * phi) * (0.5 * h);
     const double q1 = (fma(cs.E_w, c1, cs.E_dc) + cs.B * phi) * (0.5 * h);
 
-    const int ld = cs.ld;
-    T* __restrict__ xa = A.xa + m;
-    T* __restrict__ xb = A.xb + m;
-    const T* __restrict__ ya = A.ya + m;
-    const T* __restrict__ yb = A.yb + m;
+    const uint32_t rb = static_cast<uint32_t>(cs.ld) * sizeof(T);
+    const uint32_t cb = static_cast<uint32_t>(m + kPadCols) * sizeof(T);
+    const uint32_t pb = static_cast<uint32_t>(cs.nx + 2 * kPadRows) * rb;
+    const RowAddr<T> xa(A.xa, pb, rb, cb);
+    const RowAddr<T> xb(A.xb, pb, rb, cb);
+    const RowAddr<T> ya(A.ya, pb, rb, cb);
+    const RowAddr<T> yb(A.yb, pb, rb, cb);
 
-    double ya0 = ld_state(ya + (r0 - 1) * ld), yb0 = ld_state(yb + (r0 - 1) * ld);
-    double yal0 = shfl_from_left(ya0), yar0 = shfl_from_right(ya0);
-    double ybl0 = shfl_from_left(yb0), ybr0 = shfl_from_right(yb0);
-    double ya1 = ld_state(ya + r0 * ld), yb1 = ld_state(yb + r0 * ld);
-    double yal1 = shfl_from_left(ya1), yar1 = shfl_from_right(ya1);
-    double ybl1 = shfl_from_left(yb1), ybr1 = shfl_from_right(yb1);
+    // differences of Y for rows n-1 (0) and n (1); row n+1 loaded per iteration
+    double da0 = dphi_diff(ya.load(r0 - 1)), db0 = dphi_diff(yb.load(r0 - 1));
+    double da1 = dphi_diff(ya.load(r0)), db1 = dphi_diff(yb.load(r0));
+    double pf_ya = ya.load(r0 + 1), pf_yb = yb.load(r0 + 1);
+    double pf_xa = xa.load(r0), pf_xb = xb.load(r0);
 
     for (int n = r0; n < r1; ++n) {
-        const double ya2 = ld_state(ya + (n + 1) * ld), yb2 = ld_state(yb + (n + 1) * ld);
-        const double yal2 = shfl_from_left(ya2), yar2 = shfl_from_right(ya2);
-        const double ybl2 = shfl_from_left(yb2), ybr2 = shfl_from_right(yb2);
+        const double da2 = dphi_diff(pf_ya), db2 = dphi_diff(pf_yb);
+        const double a = pf_xa, b = pf_xb;
+        {
+            const int jn = min(n + 2, r1);
+            pf_ya = ya.load(jn);
+            pf_yb = yb.load(jn);
+            const int jx = min(n + 1, r1 - 1);
+            pf_xa = xa.load(jx);
+            pf_xb = xb.load(jx);
+        }
         const double chi = (n == 1) ? 2.0 : 1.0;
-        const double At = c * (chi * (yar0 - yal0) - yar2 + yal2);
-        const double Bt = c * ((ybr2 - ybl2) - ybr0 + ybl0);
         const double nd = static_cast<double>(n);
         double an, bn;
-        const double a = ld_state(xa + n * ld);
-        const double b = ld_state(xb + n * ld);
-        op_T(a, b, At, Bt, A.s_n[n] * gm * h, nd * q0, nd * q1, nu, xi, an, bn);
+        op_T(a, b, c * (chi * da0 - da2), c * (db2 - db0), lane_bcast(s_lane, n - r0) * gh, nd * q0, nd * q1, nu,
+             xi, an, bn);
         if (out_lane) {
-            st_state(xa + n * ld, an);
-            st_state(xb + n * ld, n >= 1 ? bn : 0.0);
+            xa.store(n, an);
+            xb.store(n, n >= 1 ? bn : 0.0);
             if (n == 1 && acc_step) {
                 A.acc_v[m] += bn;
                 A.acc_vc[m] += bn * cw_acc;
             }
         }
-        yal0 = yal1; yar0 = yar1; ybl0 = ybl1; ybr0 = ybr1;
-        yal1 = yal2; yar1 = yar2; ybl1 = ybl2; ybr1 = ybr2;
+        da0 = da1; db0 = db1;
+        da1 = da2; db1 = db2;
     }
 }
 
@@ -346,6 +485,19 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce_obs(Consts cs, const 
 
 inline int round_up8(int x) { return (x + 7) & ~7; }
 
+// logical (0,0) pointer -> physical plane base (row -kPadRows, column -kPadCols)
+template <typename T>
+T* phys(T* p, const Consts& cs)
+{
+    return p - (static_cast<ptrdiff_t>(kPadRows) * cs.ld + kPadCols);
+}
+
+template <typename T>
+Planes<T> phys(Planes<T> p, const Consts& cs)
+{
+    return Planes<T>{phys(p.a_h, cs), phys(p.b_h, cs), phys(p.a_f, cs), phys(p.b_f, cs)};
+}
+
 }  // namespace
 
 template <typename T>
@@ -354,8 +506,8 @@ hipError_t launch_fused_step(const Consts& cs, const Shape& sh, Planes<T> src, P
                              double* acc_vc, const Ctl* ctl, int j_off, hipStream_t st)
 {
     FusedArgs<T> A;
-    A.src = src;
-    A.dst = dst;
+    A.src = phys(src, cs);
+    A.dst = phys(dst, cs);
     A.s_n = s_n;
     A.g_m = g_m;
     A.acc_v = acc_v;
@@ -368,7 +520,7 @@ hipError_t launch_fused_step(const Consts& cs, const Shape& sh, Planes<T> src, P
     A.ntiles = A.nchunks * ((cs.ny + kFusedCols - 1) / kFusedCols);
     const int wpb = sh.waves_per_block;
     const int blocks = round_up8((A.ntiles + wpb - 1) / wpb);
-    hipLaunchKernelGGL(k_fused_step<T>, dim3(blocks), dim3(wpb * kWave), 0, st, A);
+    hipLaunchKernelGGL(k_fused_step<T>, dim3(blocks), dim3(wpb * kWave), 0, st, A, s_n);
     return hipGetLastError();
 }
 
@@ -379,10 +531,10 @@ hipError_t launch_half_step(const Consts& cs, const Shape& sh, T* xa, T* xb, con
                             const Ctl* ctl, int j_off, hipStream_t st)
 {
     HalfArgs<T> A;
-    A.xa = xa;
-    A.xb = xb;
-    A.ya = ya;
-    A.yb = yb;
+    A.xa = phys(xa, cs);
+    A.xb = phys(xb, cs);
+    A.ya = phys(ya, cs);
+    A.yb = phys(yb, cs);
     A.s_n = s_n;
     A.g_m = g_m;
     A.acc_v = acc_v;
@@ -399,7 +551,7 @@ hipError_t launch_half_step(const Consts& cs, const Shape& sh, T* xa, T* xb, con
     A.ntiles = A.nchunks * ((cs.ny + kHalfCols - 1) / kHalfCols);
     const int wpb = sh.waves_per_block;
     const int blocks = round_up8((A.ntiles + wpb - 1) / wpb);
-    hipLaunchKernelGGL(k_half_step<T>, dim3(blocks), dim3(wpb * kWave), 0, st, A);
+    hipLaunchKernelGGL(k_half_step<T>, dim3(blocks), dim3(wpb * kWave), 0, st, A, s_n);
     return hipGetLastError();
 }
 

@@ -45,6 +45,9 @@ bte_status fail(bte_status st, const char* fmt, ...)
     } while (0)
 
 constexpr double kPi = 3.14159265358979323846;
+// A wave keeps the source coefficients of its rows (plus one halo row on each
+// side) one per lane.
+constexpr int kMaxRowsPerWave = bte::kWave - 2;
 constexpr size_t kAlign = 256;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
@@ -131,7 +134,14 @@ bte_status validate(const bte_grid* g, const bte_params* p)
     if (p->omega < 0) return fail(BTE_EINVAL, "omega must be >= 0");
     if (p->precision != BTE_FP64 && p->precision != BTE_FP32_BULK)
         return fail(BTE_EINVAL, "unknown precision %d", p->precision);
+    if (g->n_x > 16384 || g->n_y > (1 << 24)) return fail(BTE_EINVAL, "grid too large");
     if (p->flags != 0) return fail(BTE_EINVAL, "flags must be 0");
+    {
+        // kernels address a plane with 32-bit byte offsets
+        const Layout L = make_layout(*g, p->precision);
+        if (static_cast<double>(L.rows) * L.ld * L.elem >= 2147483648.0)
+            return fail(BTE_EINVAL, "grid too large: one state plane must stay below 2 GiB");
+    }
     const double dphi = (g->phiy_max - g->phiy_min) / (g->n_y - 1);
     const double cfl = p->dt * std::fabs(p->B) / (2.0 * dphi);
     if (!(cfl < 1.0))
@@ -199,13 +209,13 @@ bte_tuning default_tuning(const bte_grid& g)
 {
     bte_tuning t{};
     t.kernel = BTE_KERNEL_FUSED;
-    // Enough waves to fill 256 CUs several times over, without chunks so
-    // short that the halo rows dominate.
+    // Enough wavefronts to cover the 256 CUs several times over, without
+    // chunks so short that the two halo harmonics dominate.
     const long cols = (g.n_y + bte::kFusedCols - 1) / bte::kFusedCols;
-    int R = 32;
-    while (R > 4 && cols * ((g.n_x + R - 1) / R) < 4096) R /= 2;
+    int R = 24;
+    while (R > 4 && cols * ((g.n_x + R - 1) / R) < 2048) R = R > 8 ? R / 2 + R / 4 : R - 2;
     t.rows_per_wave = std::min(R, g.n_x);
-    t.waves_per_block = 4;
+    t.waves_per_block = 1;
     const double cells = static_cast<double>(g.n_x) * g.n_y;
     t.graph_steps = cells < 4e6 ? 64 : 16;
     return t;
@@ -215,8 +225,8 @@ bte_status check_tuning(const bte_tuning& t)
 {
     if (t.kernel != BTE_KERNEL_FUSED && t.kernel != BTE_KERNEL_TWO_PASS)
         return fail(BTE_EINVAL, "unknown kernel form %d", t.kernel);
-    if (t.rows_per_wave < 1 || t.rows_per_wave > 256)
-        return fail(BTE_EINVAL, "rows_per_wave must be in 1..256");
+    if (t.rows_per_wave < 1 || t.rows_per_wave > kMaxRowsPerWave)
+        return fail(BTE_EINVAL, "rows_per_wave must be in 1..%d", kMaxRowsPerWave);
     if (t.waves_per_block != 1 && t.waves_per_block != 2 && t.waves_per_block != 4 &&
         t.waves_per_block != 8)
         return fail(BTE_EINVAL, "waves_per_block must be 1, 2, 4 or 8");
