@@ -30,10 +30,21 @@ sys.path.insert(0, HERE)
 
 HBM_PEAK_GBS = 8000.0
 
-# Algorithmic bytes per cell and launch: the fused step reads and writes the
-# four state values of both grids once (8 values); a single half-step reads
-# its own two values and the other grid's two and writes two (6 values).
-VALUES_PER_CELL = {0: 8, 1: 6}   # kernel form -> state values moved per launch
+# Algorithmic bytes per cell and launch: the fused kernels read and write the
+# four state values of both grids once per launch (8 values; the two-step
+# kernel covers two steps with them); a single half-step reads its own two
+# values and the other grid's two and writes two (6 values).
+VALUES_PER_CELL = {0: 8, 1: 6, 2: 8}      # kernel form -> state values moved per launch
+KERNEL_NAMES = {0: "k_fused_step", 1: "k_half_step", 2: "k_fused_step2"}
+FORM_NAMES = {"fused": 0, "two_pass": 1, "fused2": 2, "auto": -1}
+
+
+def launches_for(kernel, steps):
+    if kernel == 1:
+        return 2 * steps
+    if kernel == 2:
+        return steps // 2 + steps % 2
+    return steps
 
 
 def parse():
@@ -43,7 +54,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--workload", default="large_512x8193")
     ap.add_argument("--precision", choices=("fp64", "fp32"), default="fp64")
-    ap.add_argument("--kernel", choices=("fused", "two_pass"), default="fused")
+    ap.add_argument("--kernel", choices=tuple(FORM_NAMES), default="auto",
+                    help="kernel form; auto = whichever the autotuner finds fastest")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=0)
@@ -60,13 +72,13 @@ def time_solver(bte, torch, w, precision, kernel, steps, warmup, autotune=True, 
     s = bte.Solver.from_workload(w, precision=precision)
     tuned_us = None
     if shape:
-        s.set_tuning(kernel=kernel, rows_per_wave=shape[0], waves_per_block=shape[1])
+        s.set_tuning(kernel=max(kernel, 0), rows_per_wave=shape[0], waves_per_block=shape[1])
     elif autotune:
-        # outside the timed region: pick the launch shape by measurement, then
-        # keep the requested kernel form with the best shape found for it
+        # outside the timed region: pick the launch shape (and, for kernel -1,
+        # the kernel form) by measurement
         _, tuned_us = s.autotune(kernel_form=kernel)
     else:
-        s.set_tuning(kernel=kernel)
+        s.set_tuning(kernel=max(kernel, 0))
     s.step(warmup)
     torch.cuda.synchronize()
     start = torch.cuda.Event(enable_timing=True)
@@ -82,15 +94,16 @@ def time_solver(bte, torch, w, precision, kernel, steps, warmup, autotune=True, 
     obs = s.observables()
     tune = s.tuning()
     elem = 4 if precision == 1 else 8
-    launches_per_step = 1 if kernel == 0 else 2
-    bytes_per_launch = VALUES_PER_CELL[kernel] * elem * w.nx * w.ny
-    avg_launch_s = ms * 1e-3 / (steps * launches_per_step)
+    form = tune.kernel
+    bytes_per_launch = VALUES_PER_CELL[form] * elem * w.nx * w.ny
+    avg_launch_s = ms * 1e-3 / launches_for(form, steps)
     out = {
         "ms": ms, "wall_s": wall, "steps": steps,
         "cell_steps_per_s": w.nx * w.ny * steps / (ms * 1e-3),
         "us_per_step": ms * 1e3 / steps,
         "avg_launch_us": avg_launch_s * 1e6,
         "bytes_per_launch": bytes_per_launch,
+        "kernel": KERNEL_NAMES[form], "steps_per_launch": 2 if form == 2 else 1,
         "achieved_GBs": bytes_per_launch / avg_launch_s / 1e9,
         "status": int(obs.status), "v_dr": obs.v_dr, "norm": obs.norm,
         "autotune_best_us_per_step": tuned_us,
@@ -99,6 +112,10 @@ def time_solver(bte, torch, w, precision, kernel, steps, warmup, autotune=True, 
     }
     s.close()
     return out
+
+
+def main_run_form(run):
+    return run["tuning"]["kernel"]
 
 
 def cpu_baseline(w, sample_steps):
@@ -136,7 +153,7 @@ def main():
 
     w = W.WORKLOADS[args.workload]
     precision = 1 if args.precision == "fp32" else 0
-    kernel = 0 if args.kernel == "fused" else 1
+    kernel = FORM_NAMES[args.kernel]
     at = not args.no_autotune
     shape = (args.rows_per_wave, args.waves_per_block) if args.rows_per_wave > 0 else None
     main_run = time_solver(bte, torch, w, precision, kernel, args.steps, args.warmup, at, shape)
@@ -146,11 +163,13 @@ def main():
         other = 1 - precision
         variants[f"{w.name}_{'fp32' if other else 'fp64'}"] = time_solver(
             bte, torch, w, other, kernel, args.steps, args.warmup, at)
-        variants[f"{w.name}_{args.precision}_two_pass" if kernel == 0 else f"{w.name}_fused"] = \
-            time_solver(bte, torch, w, precision, 1 - kernel, args.steps, args.warmup, at)
+        for name, form in (("fused", 0), ("two_pass", 1)):
+            if form != main_run_form(main_run):
+                variants[f"{w.name}_{args.precision}_{name}"] = time_solver(
+                    bte, torch, w, precision, form, args.steps, args.warmup, at)
         c = W.CROSSED
-        variants[f"{c.name}_fp64"] = time_solver(bte, torch, c, 0, 0, 20000, 2000, at)
-        variants[f"{c.name}_fp32"] = time_solver(bte, torch, c, 1, 0, 20000, 2000, at)
+        variants[f"{c.name}_fp64"] = time_solver(bte, torch, c, 0, -1, 20000, 2000, at)
+        variants[f"{c.name}_fp32"] = time_solver(bte, torch, c, 1, -1, 20000, 2000, at)
 
     ms = main_run["ms"]
     line = {
@@ -164,19 +183,21 @@ def main():
         "data": "synthetic (seeded parameters; state from the Boltzmann equilibrium)",
         "config": {"workload": w.name, "n_x": w.nx, "n_y": w.ny, "dt": w.dt, "mu": w.mu,
                    "E_dc": w.E_dc, "E_w": w.E_w, "omega": w.omega, "B": w.B,
-                   "precision": args.precision, "kernel": args.kernel,
+                   "precision": args.precision, "kernel": main_run["kernel"],
                    "tuning": main_run["tuning"]},
         "roofline": {"bound": "hbm", "achieved": main_run["achieved_GBs"], "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": main_run["achieved_GBs"] / HBM_PEAK_GBS,
                      "traffic": None,
-                     "kernel": "k_fused_step" if kernel == 0 else "k_half_step",
+                     "kernel": main_run["kernel"],
+                     "steps_per_launch": main_run["steps_per_launch"],
                      "bytes_per_launch": main_run["bytes_per_launch"],
                      "avg_launch_us": main_run["avg_launch_us"]},
         "status": main_run["status"],
     }
     if variants:
         line["variants"] = {k: {kk: v[kk] for kk in ("cell_steps_per_s", "us_per_step",
-                                                      "achieved_GBs", "avg_launch_us", "tuning")}
+                                                      "achieved_GBs", "avg_launch_us", "kernel",
+                                                      "tuning")}
                             for k, v in variants.items()}
     if args.copy_mib > 0:
         # a plain device-to-device copy of known size, for scaling the HBM

@@ -61,8 +61,11 @@ typedef enum {
 typedef enum {
     BTE_KERNEL_FUSED = 0,    /* one launch per step: whole + fractional half-steps
                                 fused, ping-pong state buffers */
-    BTE_KERNEL_TWO_PASS = 1  /* two launches per step, each half-step in place
+    BTE_KERNEL_TWO_PASS = 1, /* two launches per step, each half-step in place
                                 (the paper's two-kernel structure) */
+    BTE_KERNEL_FUSED2 = 2    /* one launch per two steps: four half-steps chained
+                                in registers, ping-pong state buffers (an odd
+                                step count ends with one BTE_KERNEL_FUSED step) */
 } bte_kernel;
 
 typedef struct {
@@ -89,7 +92,7 @@ typedef struct {
    for the grid; bte_tune() picks one by measurement. */
 typedef struct {
     int32_t kernel;          /* bte_kernel */
-    int32_t rows_per_wave;   /* harmonics handled by one wavefront, 1 .. 62 */
+    int32_t rows_per_wave;   /* harmonics handled by one wavefront, 1 .. 62 (58 for FUSED2) */
     int32_t waves_per_block; /* 1, 2, 4 or 8 */
     int32_t graph_steps;     /* steps per captured HIP graph (even), 0 = no graph */
 } bte_tuning;
@@ -157,7 +160,7 @@ bte_status bte_get_tuning(const bte_solver* s, bte_tuning* t);
 /* Autotuner: pick the launch shape by measurement.  Builds a scratch solver
    for (grid, params) on `workspace` (bte_workspace_bytes of them; its contents
    are overwritten), times each candidate shape -- kernel form (`kernel_form`
-   = a bte_kernel value, or -1 for both), 2..62 harmonics per wavefront, 1..8
+   = a bte_kernel value, or -1 for all), 2..62 harmonics per wavefront, 1..8
    wavefronts per block -- for about `target_ms` milliseconds (<= 0: 2 ms)
    with HIP events on `hip_stream`, and writes the fastest to *best and its
    time per step to *best_us_per_step (may be NULL).  The paper tunes its

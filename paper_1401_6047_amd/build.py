@@ -16,6 +16,9 @@ ARCH = os.environ.get("BTE_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
+    # every product and sum rounds as written (explicit fma() calls stay fused),
+    # so all kernel forms and launch shapes produce identical bits
+    "-ffp-contract=off",
     "-Wall", "-Wno-unused-result",
     # never let the compiler form packed FP32 arithmetic
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

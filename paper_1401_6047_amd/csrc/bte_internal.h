@@ -14,14 +14,24 @@ namespace bte {
 //   column m of the paper's phi_y lattice stored at physical column m + kPadCols.
 // Everything outside 0 <= n < n_x, 0 <= m < n_y is zero and never written, so
 // the stencil's boundary conditions (zero cells around the box) cost no branch.
-constexpr int kPadRows = 2;
-constexpr int kPadCols = 2;
+constexpr int kPadRows = 4;
+constexpr int kPadCols = 4;
 constexpr int kWave = 64;
-// Output columns of one wavefront: the fused step needs two halo lanes on each
-// side (whole-grid values are recomputed one column beyond the outputs), the
-// single half-step one.
-constexpr int kFusedCols = kWave - 4;
+// Output columns of one wavefront.  A half-step needs the other grid one
+// column beyond its outputs, so a tile chaining h half-steps in registers
+// keeps h halo lanes on each side: the single half-step h = 1, the fused
+// step h = 2, the two-step kernel h = 4.
 constexpr int kHalfCols = kWave - 2;
+constexpr int kFusedCols = kWave - 4;
+constexpr int kFused2Cols = kWave - 8;
+
+// Largest physical column (m + kPadCols) any tile of a kernel with `cols`
+// output columns and `halo` halo lanes touches for an N_y-column grid, + 1.
+inline int col_extent(int ny, int cols, int halo)
+{
+    const int tiles = (ny + cols - 1) / cols;
+    return (tiles - 1) * cols - halo + kWave - 1 + kPadCols + 1;
+}
 
 // Device-resident control block, read by every step kernel.  Keeping the step
 // counter on the device lets one captured graph be replayed for any k.
@@ -67,6 +77,13 @@ template <typename T>
 hipError_t launch_fused_step(const Consts& cs, const Shape& sh, Planes<T> src, Planes<T> dst,
                              const double* s_n, const double* g_m, double* acc_v,
                              double* acc_vc, const Ctl* ctl, int j_off, hipStream_t st);
+
+// Two fused leap-frog steps k -> k+2 in one pass (four half-steps chained in
+// registers), from `src` to `dst`.  The step index is ctl->k + j_off.
+template <typename T>
+hipError_t launch_fused_step2(const Consts& cs, const Shape& sh, Planes<T> src, Planes<T> dst,
+                              const double* s_n, const double* g_m, double* acc_v,
+                              double* acc_vc, const Ctl* ctl, int j_off, hipStream_t st);
 
 // One half-step in place: X <- T(X; coupling from Y) with step h between
 // half-step times 2*(ctl->k + j_off) + off0 and 2*(ctl->k + j_off) + off1.

@@ -21,6 +21,8 @@
 // so 60 of the 64 lanes produce output and the tile never waits for another.
 // Reads and writes go to different (ping-pong) buffers.
 
+#include <algorithm>
+
 #include "bte_internal.h"
 
 namespace bte {
@@ -125,15 +127,53 @@ __device__ __forceinline__ int wave_tile()
 // plane's size: an access outside the plane reads 0 and a store is dropped.
 constexpr int kBufferWord3 = 0x00020000;   // gfx9 raw buffer, no format conversion
 
+// ---- FP32 storage with stochastic rounding -------------------------------------
+// In FP32-bulk mode every cell update is computed in FP64 and stored in FP32.
+// Round-to-nearest would make the storage error of a slowly drifting state
+// systematic: a step changes a value by ~dt of itself, only a few float ulp,
+// and the same rounding direction repeats step after step.  Stochastic
+// rounding (round up with probability equal to the discarded fraction) makes
+// each storage error zero-mean and independent, so the errors average out in
+// the drift velocity and absorption.  The random bits come from a
+// counter-based hash of (step, plane, cell), so runs are reproducible.
+__device__ __forceinline__ uint32_t mix32(uint32_t x)
+{
+    x ^= x >> 16;
+    x *= 0x7feb352dU;
+    x ^= x >> 15;
+    x *= 0x846ca68bU;
+    x ^= x >> 16;
+    return x;
+}
+
+// Per-launch, per-plane seed.
+__device__ __forceinline__ uint32_t plane_seed(int64_t k, uint32_t tag)
+{
+    const uint32_t lo = static_cast<uint32_t>(k), hi = static_cast<uint32_t>(static_cast<uint64_t>(k) >> 32);
+    return mix32(mix32(lo * 0x9E3779B9U + hi) ^ (tag * 0x85EBCA6BU + 0x27D4EB2FU));
+}
+
+// FP64 -> FP32 with stochastic rounding: add 29 random bits below the float
+// mantissa of the double's bit pattern, truncate them, convert (now exact).
+__device__ __forceinline__ float round_stochastic(double x, uint32_t rnd)
+{
+    uint64_t b = static_cast<uint64_t>(__double_as_longlong(x));
+    b += static_cast<uint64_t>(rnd >> 3);
+    b &= ~((static_cast<uint64_t>(1) << 29) - 1);
+    return static_cast<float>(__longlong_as_double(static_cast<long long>(b)));
+}
+
 template <typename T>
 struct RowAddr {
     __amdgpu_buffer_rsrc_t rsrc;
     uint32_t row_bytes;   // ld * sizeof(T)
     uint32_t col_bytes;   // (m + kPadCols) * sizeof(T), per lane
-    __device__ __forceinline__ RowAddr(const T* base, uint32_t plane_bytes, uint32_t rb, uint32_t cb)
+    uint32_t seed;        // stochastic-rounding seed of this plane and launch (FP32 only)
+    __device__ __forceinline__ RowAddr(const T* base, uint32_t plane_bytes, uint32_t rb, uint32_t cb,
+                                       uint32_t sd = 0)
         : rsrc(__builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(base), static_cast<short>(0),
                                                  static_cast<int>(plane_bytes), kBufferWord3)),
-          row_bytes(rb), col_bytes(cb)
+          row_bytes(rb), col_bytes(cb), seed(sd)
     {
     }
     __device__ __forceinline__ int soff(int j) const
@@ -157,7 +197,8 @@ struct RowAddr {
             __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, x), rsrc, col_bytes, soff(j), 0);
         } else {
             using V = decltype(__builtin_amdgcn_raw_buffer_load_b32(rsrc, 0u, 0, 0));
-            const float f = static_cast<float>(x);
+            const uint32_t cell = static_cast<uint32_t>(soff(j)) + col_bytes;
+            const float f = round_stochastic(x, mix32(seed ^ cell));
             __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(V, f), rsrc, col_bytes, soff(j), 0);
         }
     }
@@ -228,10 +269,10 @@ __global__ __launch_bounds__(512) void k_fused_step(FusedArgs<T> A, const double
     const RowAddr<T> bHs(A.src.b_h, pb, rb, cb);
     const RowAddr<T> aFs(A.src.a_f, pb, rb, cb);
     const RowAddr<T> bFs(A.src.b_f, pb, rb, cb);
-    const RowAddr<T> aHd(A.dst.a_h, pb, rb, cb);
-    const RowAddr<T> bHd(A.dst.b_h, pb, rb, cb);
-    const RowAddr<T> aFd(A.dst.a_f, pb, rb, cb);
-    const RowAddr<T> bFd(A.dst.b_f, pb, rb, cb);
+    const RowAddr<T> aHd(A.dst.a_h, pb, rb, cb, plane_seed(k, 0));
+    const RowAddr<T> bHd(A.dst.b_h, pb, rb, cb, plane_seed(k, 1));
+    const RowAddr<T> aFd(A.dst.a_f, pb, rb, cb, plane_seed(k, 2));
+    const RowAddr<T> bFd(A.dst.b_f, pb, rb, cb, plane_seed(k, 3));
 
     // Sliding window over harmonics.  Iteration j computes the new whole grid
     // at harmonic j (needs old fractional rows j-1, j+1) and the new
@@ -330,6 +371,200 @@ __global__ __launch_bounds__(512) void k_fused_step(FusedArgs<T> A, const double
     }
 }
 
+// ---- two steps per pass ------------------------------------------------------
+// Registers of one slot (rows congruent mod 3) of the two-step pipeline.
+struct Row2Regs {
+    double f0a, f0b, f0da, f0db;   // old fractional grid z^{k+1/2}: own, phi_y differences
+    double h1a, h1b, h1da, h1db;   // whole grid z^{k+1}: own, differences
+    double f1a, f1b, f1da, f1db;   // fractional grid z^{k+3/2}: own, differences
+    double h2da, h2db;             // whole grid z^{k+2}: differences
+    double nfa, nfb, nha, nhb;     // loads in flight (old fractional row j+1, old whole row j)
+};
+
+// Two leap-frog steps in one pass over the state.  Iteration j of the march
+// along the harmonics computes
+//   W1: z^{k+1}   at harmonic j    (old fractional rows j-1, j+1; old whole row j)
+//   F1: z^{k+3/2} at harmonic j-1  (z^{k+1} rows j-2, j; old fractional row j-1)
+//   W2: z^{k+2}   at harmonic j-2  (z^{k+3/2} rows j-3, j-1; z^{k+1} row j-2)
+//   F2: z^{k+5/2} at harmonic j-3  (z^{k+2} rows j-4, j-2; z^{k+3/2} row j-3)
+// and writes z^{k+2} and z^{k+5/2}: the state is read and written once per two
+// steps.  Every quantity a later stage needs lives in the slot of its row mod
+// 3.  The tile keeps four halo lanes and three or four halo harmonics on each
+// side; each stage is valid one lane further in, and the 56 lanes 4..59 hold
+// outputs.  Per cell the arithmetic is exactly that of the one-step kernel.
+template <typename T>
+__global__ __launch_bounds__(256) void k_fused_step2(FusedArgs<T> A, const double* __restrict__ s_n)
+{
+    const Consts& cs = A.cs;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int tile = wave_tile();
+    if (tile >= A.ntiles) return;                    // wave-uniform
+    const int ct = tile / A.nchunks;
+    const int r0 = (tile - ct * A.nchunks) * A.R;
+    const int r1 = min(r0 + A.R, cs.nx);
+    const int m = ct * kFused2Cols - 4 + lane;
+    const bool col_ok = (m >= 0) && (m < cs.ny);
+    const bool out_lane = (lane >= 4) && (lane < kWave - 4) && col_ok;
+
+    const Ctl ctl = *A.ctl;
+    const int64_t k = ctl.k + A.j_off;
+    // cos(omega t) at the half-step times 2k .. 2k+5, lane i holds time 2k+i
+    double cw[6];
+    {
+        const double t = static_cast<double>(2 * k + min(lane, 5)) * cs.half_dt;
+        const double v = cos(cs.omega * t);
+#pragma unroll
+        for (int i = 0; i < 6; ++i) cw[i] = __shfl(v, i);
+    }
+    const bool acc1 = (k + 1 > ctl.win_lo) && (k + 1 <= ctl.win_hi);
+    const bool acc2 = (k + 2 > ctl.win_lo) && (k + 2 <= ctl.win_hi);
+
+    const double phi = fma(static_cast<double>(m), cs.dphi, cs.phimin);
+    const double gdt = (col_ok ? A.g_m[m] : 0.0) * cs.dt;
+    const double hdt = 0.5 * cs.dt;
+    double q[6];                                      // (E(t_i) + B phi) dt/2
+#pragma unroll
+    for (int i = 0; i < 6; ++i) q[i] = (fma(cs.E_w, cw[i], cs.E_dc) + cs.B * phi) * hdt;
+    const double c = cs.c_full, nu = cs.nu, xi = cs.xi;
+    // s_n of harmonics r0-3 .. r0+60, one per lane
+    const int sbase = r0 - 3;
+    const double s_lane = s_n[min(max(sbase + lane, 0), cs.nx - 1)];
+    auto s_of = [&](int n) { return lane_bcast(s_lane, min(max(n - sbase, 0), kWave - 1)); };
+
+    const uint32_t rb = static_cast<uint32_t>(cs.ld) * sizeof(T);
+    const uint32_t cb = static_cast<uint32_t>(m + kPadCols) * sizeof(T);
+    const uint32_t pb = static_cast<uint32_t>(cs.nx + 2 * kPadRows) * rb;
+    const RowAddr<T> aHs(A.src.a_h, pb, rb, cb);
+    const RowAddr<T> bHs(A.src.b_h, pb, rb, cb);
+    const RowAddr<T> aFs(A.src.a_f, pb, rb, cb);
+    const RowAddr<T> bFs(A.src.b_f, pb, rb, cb);
+    const RowAddr<T> aHd(A.dst.a_h, pb, rb, cb, plane_seed(k, 0));
+    const RowAddr<T> bHd(A.dst.b_h, pb, rb, cb, plane_seed(k, 1));
+    const RowAddr<T> aFd(A.dst.a_f, pb, rb, cb, plane_seed(k, 2));
+    const RowAddr<T> bFd(A.dst.b_f, pb, rb, cb, plane_seed(k, 3));
+
+    auto valid = [&](int n) { return (n >= 0) && (n < cs.nx) && col_ok; };
+    auto chi_of = [](int n) { return n == 1 ? 2.0 : 1.0; };
+
+    Row2Regs S[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) S[i] = Row2Regs{};
+    const int jlo = r0 - 3;                           // first W1 row
+    const int jhi = r1 + 2;                           // last W1 row
+    auto issue = [&](Row2Regs& P, int j) {
+        const int jf = min(j + 1, r1 + 3);
+        const int jh = min(j, jhi);
+        P.nfa = aFs.load(jf);
+        P.nfb = bFs.load(jf);
+        P.nha = aHs.load(jh);
+        P.nhb = bHs.load(jh);
+    };
+    {
+        Row2Regs& a = S[0];                           // slot of jlo - 1
+        a.f0a = aFs.load(jlo - 1);
+        a.f0b = bFs.load(jlo - 1);
+        Row2Regs& b = S[1];                           // slot of jlo
+        b.f0a = aFs.load(jlo);
+        b.f0b = bFs.load(jlo);
+        issue(S[1], jlo);
+        issue(S[2], jlo + 1);
+        issue(S[0], jlo + 2);
+        a.f0da = dphi_diff(a.f0a);
+        a.f0db = dphi_diff(a.f0b);
+        b.f0da = dphi_diff(b.f0a);
+        b.f0db = dphi_diff(b.f0b);
+    }
+
+    auto iter = [&](int j, Row2Regs& Pm, Row2Regs& P0, Row2Regs& Pp) {
+        // inputs loaded three iterations ago
+        Pp.f0a = P0.nfa;
+        Pp.f0b = P0.nfb;
+        const double ha0 = P0.nha, hb0 = P0.nhb;
+        issue(P0, j + 3);
+        Pp.f0da = dphi_diff(Pp.f0a);
+        Pp.f0db = dphi_diff(Pp.f0b);
+
+        // W1: whole grid k -> k+1 at harmonic j
+        {
+            const double nd = static_cast<double>(j);
+            double ha, hb;
+            op_T(ha0, hb0, c * (chi_of(j) * Pm.f0da - Pp.f0da), c * (Pp.f0db - Pm.f0db),
+                 s_of(j) * gdt, nd * q[0], nd * q[2], nu, xi, ha, hb);
+            const bool v = valid(j);
+            ha = v ? ha : 0.0;
+            hb = (v && j >= 1) ? hb : 0.0;
+            P0.h1a = ha;
+            P0.h1b = hb;
+            P0.h1da = dphi_diff(ha);
+            P0.h1db = dphi_diff(hb);
+            if (j == 1 && j >= r0 && j < r1 && out_lane && acc1) {
+                A.acc_v[m] += hb;
+                A.acc_vc[m] += hb * cw[2];
+            }
+        }
+        // F1: fractional grid k+1/2 -> k+3/2 at harmonic j-1
+        {
+            const int n = j - 1;
+            const double nd = static_cast<double>(n);
+            double fa, fb;
+            op_T(Pm.f0a, Pm.f0b, c * (chi_of(n) * Pp.h1da - P0.h1da), c * (P0.h1db - Pp.h1db),
+                 s_of(n) * gdt, nd * q[1], nd * q[3], nu, xi, fa, fb);
+            const bool v = valid(n);
+            fa = v ? fa : 0.0;
+            fb = (v && n >= 1) ? fb : 0.0;
+            Pm.f1a = fa;
+            Pm.f1b = fb;
+            Pm.f1da = dphi_diff(fa);
+            Pm.f1db = dphi_diff(fb);
+        }
+        // W2: whole grid k+1 -> k+2 at harmonic j-2
+        {
+            const int n = j - 2;
+            const double nd = static_cast<double>(n);
+            double ha, hb;
+            op_T(Pp.h1a, Pp.h1b, c * (chi_of(n) * P0.f1da - Pm.f1da), c * (Pm.f1db - P0.f1db),
+                 s_of(n) * gdt, nd * q[2], nd * q[4], nu, xi, ha, hb);
+            const bool v = valid(n);
+            ha = v ? ha : 0.0;
+            hb = (v && n >= 1) ? hb : 0.0;
+            Pp.h2da = dphi_diff(ha);
+            Pp.h2db = dphi_diff(hb);
+            if (n >= r0 && n < r1 && out_lane) {
+                aHd.store(n, ha);
+                bHd.store(n, hb);
+                if (n == 1 && acc2) {
+                    A.acc_v[m] += hb;
+                    A.acc_vc[m] += hb * cw[4];
+                }
+            }
+        }
+        // F2: fractional grid k+3/2 -> k+5/2 at harmonic j-3
+        {
+            const int n = j - 3;
+            if (n >= r0 && n < r1) {
+                const double nd = static_cast<double>(n);
+                double fa, fb;
+                op_T(P0.f1a, P0.f1b, c * (chi_of(n) * Pm.h2da - Pp.h2da),
+                     c * (Pp.h2db - Pm.h2db), s_of(n) * gdt, nd * q[3], nd * q[5], nu, xi, fa,
+                     fb);
+                if (out_lane) {
+                    aFd.store(n, fa);
+                    bFd.store(n, n >= 1 ? fb : 0.0);
+                }
+            }
+        }
+    };
+
+    // W1 rows jlo .. jhi (R + 6 iterations), padded to a multiple of 3 so the
+    // loop body is periodic in the slot rotation; padding iterations store nothing.
+    const int jend = jlo + (jhi - jlo + 1 + 2) / 3 * 3;
+    for (int j = jlo; j < jend; j += 3) {
+        iter(j, S[0], S[1], S[2]);
+        iter(j + 1, S[1], S[2], S[0]);
+        iter(j + 2, S[2], S[0], S[1]);
+    }
+}
+
 template <typename T>
 struct HalfArgs {
     T* xa;          // physical plane bases
@@ -388,8 +623,10 @@ __global__ __launch_bounds__(512) void k_half_step(HalfArgs<T> A, const double* 
     const uint32_t rb = static_cast<uint32_t>(cs.ld) * sizeof(T);
     const uint32_t cb = static_cast<uint32_t>(m + kPadCols) * sizeof(T);
     const uint32_t pb = static_cast<uint32_t>(cs.nx + 2 * kPadRows) * rb;
-    const RowAddr<T> xa(A.xa, pb, rb, cb);
-    const RowAddr<T> xb(A.xb, pb, rb, cb);
+    // distinct per half-step kind: start-up (0,1), whole (0,2), fractional (1,3)
+    const uint32_t tag = 4u + 2u * static_cast<uint32_t>(A.off0 + A.off1);
+    const RowAddr<T> xa(A.xa, pb, rb, cb, plane_seed(k, tag));
+    const RowAddr<T> xb(A.xb, pb, rb, cb, plane_seed(k, tag + 1));
     const RowAddr<T> ya(A.ya, pb, rb, cb);
     const RowAddr<T> yb(A.yb, pb, rb, cb);
 
@@ -525,6 +762,32 @@ hipError_t launch_fused_step(const Consts& cs, const Shape& sh, Planes<T> src, P
 }
 
 template <typename T>
+hipError_t launch_fused_step2(const Consts& cs, const Shape& sh, Planes<T> src, Planes<T> dst,
+                              const double* s_n, const double* g_m, double* acc_v,
+                              double* acc_vc, const Ctl* ctl, int j_off, hipStream_t st)
+{
+    FusedArgs<T> A;
+    A.src = phys(src, cs);
+    A.dst = phys(dst, cs);
+    A.s_n = s_n;
+    A.g_m = g_m;
+    A.acc_v = acc_v;
+    A.acc_vc = acc_vc;
+    A.ctl = ctl;
+    A.cs = cs;
+    A.j_off = j_off;
+    // the wave's source coefficients cover its R harmonics plus 3 + 3 halo
+    // harmonics, one per lane
+    A.R = std::min(sh.rows_per_wave, kWave - 6);
+    A.nchunks = (cs.nx + A.R - 1) / A.R;
+    A.ntiles = A.nchunks * ((cs.ny + kFused2Cols - 1) / kFused2Cols);
+    const int wpb = std::min(sh.waves_per_block, 4);
+    const int blocks = round_up8((A.ntiles + wpb - 1) / wpb);
+    hipLaunchKernelGGL(k_fused_step2<T>, dim3(blocks), dim3(wpb * kWave), 0, st, A, s_n);
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_half_step(const Consts& cs, const Shape& sh, T* xa, T* xb, const T* ya,
                             const T* yb, const double* s_n, const double* g_m, double h,
                             int off0, int off1, int accumulate, double* acc_v, double* acc_vc,
@@ -586,6 +849,9 @@ hipError_t launch_reduce_obs(const Consts& cs, const T* a_h, const T* b_h, const
     template hipError_t launch_fused_step<T>(const Consts&, const Shape&, Planes<T>, Planes<T>, \
                                              const double*, const double*, double*, double*,   \
                                              const Ctl*, int, hipStream_t);                    \
+    template hipError_t launch_fused_step2<T>(const Consts&, const Shape&, Planes<T>, Planes<T>, \
+                                              const double*, const double*, double*, double*,  \
+                                              const Ctl*, int, hipStream_t);                   \
     template hipError_t launch_half_step<T>(const Consts&, const Shape&, T*, T*, const T*,      \
                                             const T*, const double*, const double*, double,    \
                                             int, int, int, double*, double*, const Ctl*, int,  \

@@ -89,12 +89,8 @@ Layout make_layout(const bte_grid& g, int precision)
 {
     Layout L;
     using namespace bte;
-    const int nct_f = (g.n_y + kFusedCols - 1) / kFusedCols;
-    const int nct_h = (g.n_y + kHalfCols - 1) / kHalfCols;
-    // physical columns touched: fused lanes reach (nct_f-1)*60 + 63, half-step
-    // lanes (nct_h-1)*62 + 64.
-    int need = std::max((nct_f - 1) * kFusedCols + kWave, (nct_h - 1) * kHalfCols + kWave + 1);
-    need = std::max(need, g.n_y + 2 * kPadCols);
+    int need = std::max({col_extent(g.n_y, kHalfCols, 1), col_extent(g.n_y, kFusedCols, 2),
+                         col_extent(g.n_y, kFused2Cols, 4), g.n_y + 2 * kPadCols});
     L.ld = (need + 63) / 64 * 64;
     L.rows = g.n_x + 2 * kPadRows;
     L.elem = precision == BTE_FP32_BULK ? 4 : 8;
@@ -170,6 +166,7 @@ struct bte_solver {
     double norm0 = 0;               // normalisation of the initial state
     bool unstable = false;
     hipGraphExec_t graph[2] = {nullptr, nullptr};   // by starting set
+    bool graph_flip[2] = {false, false};            // graph ends in the other set
     int graph_steps_built = -1;
     double* pinned = nullptr;       // host landing buffer for reductions
 
@@ -223,7 +220,8 @@ bte_tuning default_tuning(const bte_grid& g)
 
 bte_status check_tuning(const bte_tuning& t)
 {
-    if (t.kernel != BTE_KERNEL_FUSED && t.kernel != BTE_KERNEL_TWO_PASS)
+    if (t.kernel != BTE_KERNEL_FUSED && t.kernel != BTE_KERNEL_TWO_PASS &&
+        t.kernel != BTE_KERNEL_FUSED2)
         return fail(BTE_EINVAL, "unknown kernel form %d", t.kernel);
     if (t.rows_per_wave < 1 || t.rows_per_wave > kMaxRowsPerWave)
         return fail(BTE_EINVAL, "rows_per_wave must be in 1..%d", kMaxRowsPerWave);
@@ -235,39 +233,51 @@ bte_status check_tuning(const bte_tuning& t)
     return BTE_OK;
 }
 
+// Queue `count` (1 or 2) steps starting at step offset j_off.
 template <typename T>
-hipError_t queue_one_step(bte_solver* s, int j_off, hipStream_t st)
+hipError_t queue_steps_of(bte_solver* s, int j_off, int count, hipStream_t st)
 {
     bte::Shape sh{s->tune.rows_per_wave, s->tune.waves_per_block};
-    if (s->tune.kernel == BTE_KERNEL_FUSED) {
-        const int src = s->cur, dst = 1 - s->cur;
-        hipError_t e = bte::launch_fused_step<T>(s->cs, sh, s->planes<T>(src), s->planes<T>(dst),
-                                                 s->s_n(), s->g_m(), s->acc_v(), s->acc_vc(),
-                                                 s->ctl(), j_off, st);
-        s->cur = dst;
-        return e;
+    if (s->tune.kernel == BTE_KERNEL_TWO_PASS) {
+        // two passes in place on the current set: whole, then fractional
+        auto P = s->planes<T>(s->cur);
+        hipError_t e = bte::launch_half_step<T>(s->cs, sh, P.a_h, P.b_h, P.a_f, P.b_f, s->s_n(),
+                                                s->g_m(), s->cs.dt, 0, 2, 1, s->acc_v(),
+                                                s->acc_vc(), s->ctl(), j_off, st);
+        if (e != hipSuccess) return e;
+        return bte::launch_half_step<T>(s->cs, sh, P.a_f, P.b_f, P.a_h, P.b_h, s->s_n(),
+                                        s->g_m(), s->cs.dt, 1, 3, 0, s->acc_v(), s->acc_vc(),
+                                        s->ctl(), j_off, st);
     }
-    // two passes in place on the current set: whole, then fractional
-    auto P = s->planes<T>(s->cur);
-    hipError_t e = bte::launch_half_step<T>(s->cs, sh, P.a_h, P.b_h, P.a_f, P.b_f, s->s_n(),
-                                            s->g_m(), s->cs.dt, 0, 2, 1, s->acc_v(),
-                                            s->acc_vc(), s->ctl(), j_off, st);
-    if (e != hipSuccess) return e;
-    return bte::launch_half_step<T>(s->cs, sh, P.a_f, P.b_f, P.a_h, P.b_h, s->s_n(), s->g_m(),
-                                    s->cs.dt, 1, 3, 0, s->acc_v(), s->acc_vc(), s->ctl(), j_off,
-                                    st);
+    const int src = s->cur, dst = 1 - s->cur;
+    hipError_t e;
+    if (count == 2)
+        e = bte::launch_fused_step2<T>(s->cs, sh, s->planes<T>(src), s->planes<T>(dst), s->s_n(),
+                                       s->g_m(), s->acc_v(), s->acc_vc(), s->ctl(), j_off, st);
+    else
+        e = bte::launch_fused_step<T>(s->cs, sh, s->planes<T>(src), s->planes<T>(dst), s->s_n(),
+                                      s->g_m(), s->acc_v(), s->acc_vc(), s->ctl(), j_off, st);
+    s->cur = dst;
+    return e;
 }
 
 hipError_t queue_steps_direct(bte_solver* s, int n, hipStream_t st)
 {
-    for (int j = 0; j < n; ++j) {
-        hipError_t e = s->fp32() ? queue_one_step<float>(s, j, st) : queue_one_step<double>(s, j, st);
+    int j = 0;
+    while (j < n) {
+        const int count = (s->tune.kernel == BTE_KERNEL_FUSED2 && n - j >= 2) ? 2 : 1;
+        hipError_t e = s->fp32() ? queue_steps_of<float>(s, j, count, st)
+                                 : queue_steps_of<double>(s, j, count, st);
         if (e != hipSuccess) return e;
+        j += count;
     }
     if (n > 0) return bte::launch_advance_counter(s->ctl(), n, st);
     return hipSuccess;
 }
 
+// Capture `graph_steps` steps starting from the current ping-pong set.  The
+// graph ends in the same set or in the other one (graph_flip), depending on
+// how many ping-pong launches it holds.
 bte_status build_graph(bte_solver* s)
 {
     const int n = s->tune.graph_steps;
@@ -277,7 +287,8 @@ bte_status build_graph(bte_solver* s)
     HIP_TRY(hipStreamBeginCapture(s->capture_stream, hipStreamCaptureModeThreadLocal));
     hipError_t e = queue_steps_direct(s, n, s->capture_stream);
     hipError_t e2 = hipStreamEndCapture(s->capture_stream, &g);
-    s->cur = start;   // capture does not execute anything; n is even
+    s->graph_flip[start] = (s->cur != start);
+    s->cur = start;   // capturing executed nothing
     if (e != hipSuccess || e2 != hipSuccess) {
         if (g) (void)hipGraphDestroy(g);
         return fail(BTE_EDEVICE, "graph capture failed: %s",
@@ -515,12 +526,13 @@ bte_status bte_step(bte_solver* s, int64_t n_steps)
             drop_graphs(s);
             s->graph_steps_built = G;
         }
-        if (!s->graph[s->cur]) {
-            bte_status st = build_graph(s);
-            if (st != BTE_OK) return st;
-        }
         while (left >= G) {
+            if (!s->graph[s->cur]) {
+                bte_status st = build_graph(s);
+                if (st != BTE_OK) return st;
+            }
             HIP_TRY(hipGraphLaunch(s->graph[s->cur], s->stream));
+            if (s->graph_flip[s->cur]) s->cur = 1 - s->cur;
             left -= G;
             s->step += G;
         }

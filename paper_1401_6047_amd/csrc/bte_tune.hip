@@ -48,7 +48,7 @@ extern "C" bte_status bte_tune(const bte_grid* grid, const bte_params* params, v
                                double target_ms, bte_tuning* best, double* best_us_per_step)
 {
     if (!best) return BTE_EINVAL;
-    if (kernel_form < -1 || kernel_form > BTE_KERNEL_TWO_PASS) return BTE_EINVAL;
+    if (kernel_form < -1 || kernel_form > BTE_KERNEL_FUSED2) return BTE_EINVAL;
     bte_solver* s = nullptr;
     bte_status rc = bte_create(grid, params, workspace, workspace_bytes, hip_stream, &s);
     if (rc != BTE_OK) return rc;
@@ -79,11 +79,12 @@ extern "C" bte_status bte_tune(const bte_grid* grid, const bte_params* params, v
     const int wpbs[] = {1, 2, 4, 8};
     bte_tuning win = base;
     double win_us = time_steps(s, base, n, st, ev);
-    for (int kernel = BTE_KERNEL_FUSED; kernel <= BTE_KERNEL_TWO_PASS; ++kernel) {
+    for (int kernel = BTE_KERNEL_FUSED; kernel <= BTE_KERNEL_FUSED2; ++kernel) {
         if (kernel_form >= 0 && kernel != kernel_form) continue;
         for (int R : rows) {
             if (R > grid->n_x && R != rows[0]) continue;
             for (int w : wpbs) {
+                if (kernel == BTE_KERNEL_FUSED2 && (R > 58 || w > 4)) continue;
                 bte_tuning t{};
                 t.kernel = kernel;
                 t.rows_per_wave = std::min(R, grid->n_x);

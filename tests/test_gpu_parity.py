@@ -96,6 +96,11 @@ TUNINGS = [
     dict(kernel=1),
     dict(kernel=1, rows_per_wave=5, waves_per_block=1, graph_steps=0),
     dict(kernel=1, rows_per_wave=62, waves_per_block=8, graph_steps=16),
+    dict(kernel=2),
+    dict(kernel=2, rows_per_wave=1, waves_per_block=1, graph_steps=0),
+    dict(kernel=2, rows_per_wave=5, waves_per_block=2, graph_steps=2),
+    dict(kernel=2, rows_per_wave=58, waves_per_block=4, graph_steps=64),
+    dict(kernel=2, rows_per_wave=13, waves_per_block=8, graph_steps=6),
 ]
 
 
@@ -126,7 +131,7 @@ RAGGED = [(2, 3), (3, 5), (5, 61), (7, 65), (9, 119), (33, 121), (17, 187), (64,
 
 
 @pytest.mark.parametrize("nx,ny", RAGGED)
-@pytest.mark.parametrize("kernel", [0, 1])
+@pytest.mark.parametrize("kernel", [0, 1, 2])
 def test_ragged_grids_random_state(bte, nx, ny, kernel):
     w = W.random_params(1000 + nx * 7 + ny, nx=nx, ny=ny, phi=6.0, dt=2e-3)
     a, b = W.smooth_state(nx * 31 + ny, nx, ny, phi=6.0)
@@ -180,11 +185,14 @@ def test_resume_is_bitwise_and_matches_oracle(bte):
 
 
 def test_graph_and_direct_launches_agree_bitwise(bte):
+    """Graph replays, direct launches, the one- and two-step kernels and the
+    two-pass form give the same FP64 bits (same arithmetic per cell)."""
     w = W.random_params(5, nx=24, ny=200, dt=1e-3)
     outs = []
-    for g in (0, 2, 32):
-        _, st = run_gpu(bte, w, 97, tuning=dict(graph_steps=g))
-        outs.append(st)
+    for kern in (0, 2, 1):
+        for g in (0, 2, 32):
+            _, st = run_gpu(bte, w, 97, tuning=dict(kernel=kern, graph_steps=g))
+            outs.append(st)
     for st in outs[1:]:
         for x, y in zip(outs[0], st):
             np.testing.assert_array_equal(x, y)
