@@ -22,6 +22,7 @@
 // Reads and writes go to different (ping-pong) buffers.
 
 #include <algorithm>
+#include <type_traits>
 
 #include "bte_internal.h"
 
@@ -392,11 +393,27 @@ struct Row2Regs {
 // 3.  The tile keeps four halo lanes and three or four halo harmonics on each
 // side; each stage is valid one lane further in, and the 56 lanes 4..59 hold
 // outputs.  Per cell the arithmetic is exactly that of the one-step kernel.
+// Operator T with nu^2 supplied (constant over the grid).
+__device__ __forceinline__ void op_T2(double a, double b, double At, double Bt, double a0h,
+                                      double mu0, double mu1, double nu, double nu2, double xi,
+                                      double& an, double& bn)
+{
+    const double g = fma(a, xi, fma(-b, mu0, Bt + a0h));
+    const double hh = fma(b, xi, fma(a, mu0, At));
+    const double inv = recip(fma(mu1, mu1, nu2));
+    an = fma(g, nu, -hh * mu1) * inv;
+    bn = fma(g, mu1, hh * nu) * inv;
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_fused_step2(FusedArgs<T> A, const double* __restrict__ s_n)
 {
+    // source coefficients s_n of each wave's harmonics, read with a
+    // wave-uniform index (an LDS broadcast, no vector ALU work)
+    __shared__ double s_tab[4][kWave];
     const Consts& cs = A.cs;
     const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
     const int tile = wave_tile();
     if (tile >= A.ntiles) return;                    // wave-uniform
     const int ct = tile / A.nchunks;
@@ -425,11 +442,13 @@ __global__ __launch_bounds__(256) void k_fused_step2(FusedArgs<T> A, const doubl
     double q[6];                                      // (E(t_i) + B phi) dt/2
 #pragma unroll
     for (int i = 0; i < 6; ++i) q[i] = (fma(cs.E_w, cw[i], cs.E_dc) + cs.B * phi) * hdt;
-    const double c = cs.c_full, nu = cs.nu, xi = cs.xi;
-    // s_n of harmonics r0-3 .. r0+60, one per lane
+    const double c = cs.c_full, nu = cs.nu, xi = cs.xi, nu2 = cs.nu * cs.nu;
+    // s_n of harmonics r0-3 .. r0+60, one per lane; a0 dt = s_n (g_m dt) as
+    // in the other kernel forms
     const int sbase = r0 - 3;
-    const double s_lane = s_n[min(max(sbase + lane, 0), cs.nx - 1)];
-    auto s_of = [&](int n) { return lane_bcast(s_lane, min(max(n - sbase, 0), kWave - 1)); };
+    s_tab[wave][lane] = s_n[min(max(sbase + lane, 0), cs.nx - 1)];
+    __builtin_amdgcn_wave_barrier();
+    auto a0dt = [&](int n) { return s_tab[wave][min(max(n - sbase, 0), kWave - 1)] * gdt; };
 
     const uint32_t rb = static_cast<uint32_t>(cs.ld) * sizeof(T);
     const uint32_t cb = static_cast<uint32_t>(m + kPadCols) * sizeof(T);
@@ -443,125 +462,173 @@ __global__ __launch_bounds__(256) void k_fused_step2(FusedArgs<T> A, const doubl
     const RowAddr<T> aFd(A.dst.a_f, pb, rb, cb, plane_seed(k, 2));
     const RowAddr<T> bFd(A.dst.b_f, pb, rb, cb, plane_seed(k, 3));
 
-    auto valid = [&](int n) { return (n >= 0) && (n < cs.nx) && col_ok; };
-    auto chi_of = [](int n) { return n == 1 ? 2.0 : 1.0; };
-
-    Row2Regs S[3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) S[i] = Row2Regs{};
     const int jlo = r0 - 3;                           // first W1 row
     const int jhi = r1 + 2;                           // last W1 row
-    auto issue = [&](Row2Regs& P, int j) {
-        const int jf = min(j + 1, r1 + 3);
-        const int jh = min(j, jhi);
-        P.nfa = aFs.load(jf);
-        P.nfb = bFs.load(jf);
-        P.nha = aHs.load(jh);
-        P.nhb = bHs.load(jh);
-    };
-    {
-        Row2Regs& a = S[0];                           // slot of jlo - 1
-        a.f0a = aFs.load(jlo - 1);
-        a.f0b = bFs.load(jlo - 1);
-        Row2Regs& b = S[1];                           // slot of jlo
-        b.f0a = aFs.load(jlo);
-        b.f0b = bFs.load(jlo);
-        issue(S[1], jlo);
-        issue(S[2], jlo + 1);
-        issue(S[0], jlo + 2);
-        a.f0da = dphi_diff(a.f0a);
-        a.f0db = dphi_diff(a.f0b);
-        b.f0da = dphi_diff(b.f0a);
-        b.f0db = dphi_diff(b.f0b);
-    }
+    // A tile is "interior" when every row its stages compute is a harmonic
+    // >= 2 inside the grid and every lane a phi_y column inside the box: no
+    // boundary masks, chi = 1 and no b_0 row.
+    const int ncol_tiles = (cs.ny + kFused2Cols - 1) / kFused2Cols;
+    const bool interior = (jlo >= 2) && (jhi < cs.nx) && (ct > 0) && (ct < ncol_tiles - 1) &&
+                          (ct * kFused2Cols - 4 >= 0) && (ct * kFused2Cols + kWave - 5 < cs.ny);
 
-    auto iter = [&](int j, Row2Regs& Pm, Row2Regs& P0, Row2Regs& Pp) {
-        // inputs loaded three iterations ago
-        Pp.f0a = P0.nfa;
-        Pp.f0b = P0.nfb;
-        const double ha0 = P0.nha, hb0 = P0.nhb;
-        issue(P0, j + 3);
-        Pp.f0da = dphi_diff(Pp.f0a);
-        Pp.f0db = dphi_diff(Pp.f0b);
-
-        // W1: whole grid k -> k+1 at harmonic j
-        {
-            const double nd = static_cast<double>(j);
-            double ha, hb;
-            op_T(ha0, hb0, c * (chi_of(j) * Pm.f0da - Pp.f0da), c * (Pp.f0db - Pm.f0db),
-                 s_of(j) * gdt, nd * q[0], nd * q[2], nu, xi, ha, hb);
-            const bool v = valid(j);
-            ha = v ? ha : 0.0;
-            hb = (v && j >= 1) ? hb : 0.0;
-            P0.h1a = ha;
-            P0.h1b = hb;
-            P0.h1da = dphi_diff(ha);
-            P0.h1db = dphi_diff(hb);
-            if (j == 1 && j >= r0 && j < r1 && out_lane && acc1) {
-                A.acc_v[m] += hb;
-                A.acc_vc[m] += hb * cw[2];
+    // The march over the harmonics alternates direction from one chunk to the
+    // next (even chunks upward in n, odd chunks downward), so that the halo
+    // harmonics two neighbouring chunks share are read by both at about the
+    // same time and the second read hits in L2.  Stage rows move with the
+    // direction D: W1 at j, F1 at j - D, W2 at j - 2D, F2 at j - 3D.
+    auto run = [&](auto edge_tag, auto dir_tag) {
+        constexpr bool EDGE = decltype(edge_tag)::value;
+        constexpr int D = decltype(dir_tag)::value;
+        auto valid = [&](int n) { return (n >= 0) && (n < cs.nx) && col_ok; };
+        // coupling terms of Sec. 3 from the other grid's phi_y differences
+        // at harmonics n-1 (lo) and n+1 (hi): A = c (chi lo_a - hi_a),
+        // B = c (hi_b - lo_b).  Slot "behind" holds row n - D, "ahead" n + D.
+        auto coupling = [&](int n, double behind_a, double ahead_a, double behind_b,
+                            double ahead_b, double& At, double& Bt) {
+            const double lo_a = D > 0 ? behind_a : ahead_a, hi_a = D > 0 ? ahead_a : behind_a;
+            const double lo_b = D > 0 ? behind_b : ahead_b, hi_b = D > 0 ? ahead_b : behind_b;
+            if constexpr (EDGE)
+                At = c * ((n == 1 ? 2.0 * lo_a : lo_a) - hi_a);
+            else
+                At = c * (lo_a - hi_a);
+            Bt = c * (hi_b - lo_b);
+        };
+        auto mask = [&](int n, double& a, double& b) {
+            if constexpr (EDGE) {
+                const bool v = valid(n);
+                a = v ? a : 0.0;
+                b = (v && n >= 1) ? b : 0.0;
             }
-        }
-        // F1: fractional grid k+1/2 -> k+3/2 at harmonic j-1
+        };
+
+        const int jfirst = D > 0 ? jlo : jhi;         // first W1 row of the march
+        Row2Regs S[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) S[i] = Row2Regs{};
+        auto issue = [&](Row2Regs& P, int j) {
+            const int jf = min(max(j + D, r0 - 4), r1 + 3);
+            const int jh = min(max(j, jlo), jhi);
+            P.nfa = aFs.load(jf);
+            P.nfb = bFs.load(jf);
+            P.nha = aHs.load(jh);
+            P.nhb = bHs.load(jh);
+        };
         {
-            const int n = j - 1;
-            const double nd = static_cast<double>(n);
-            double fa, fb;
-            op_T(Pm.f0a, Pm.f0b, c * (chi_of(n) * Pp.h1da - P0.h1da), c * (P0.h1db - Pp.h1db),
-                 s_of(n) * gdt, nd * q[1], nd * q[3], nu, xi, fa, fb);
-            const bool v = valid(n);
-            fa = v ? fa : 0.0;
-            fb = (v && n >= 1) ? fb : 0.0;
-            Pm.f1a = fa;
-            Pm.f1b = fb;
-            Pm.f1da = dphi_diff(fa);
-            Pm.f1db = dphi_diff(fb);
+            Row2Regs& a = S[0];                       // slot of jfirst - D
+            a.f0a = aFs.load(jfirst - D);
+            a.f0b = bFs.load(jfirst - D);
+            Row2Regs& b = S[1];                       // slot of jfirst
+            b.f0a = aFs.load(jfirst);
+            b.f0b = bFs.load(jfirst);
+            issue(S[1], jfirst);
+            issue(S[2], jfirst + D);
+            issue(S[0], jfirst + 2 * D);
+            a.f0da = dphi_diff(a.f0a);
+            a.f0db = dphi_diff(a.f0b);
+            b.f0da = dphi_diff(b.f0a);
+            b.f0db = dphi_diff(b.f0b);
         }
-        // W2: whole grid k+1 -> k+2 at harmonic j-2
-        {
-            const int n = j - 2;
-            const double nd = static_cast<double>(n);
-            double ha, hb;
-            op_T(Pp.h1a, Pp.h1b, c * (chi_of(n) * P0.f1da - Pm.f1da), c * (Pm.f1db - P0.f1db),
-                 s_of(n) * gdt, nd * q[2], nd * q[4], nu, xi, ha, hb);
-            const bool v = valid(n);
-            ha = v ? ha : 0.0;
-            hb = (v && n >= 1) ? hb : 0.0;
-            Pp.h2da = dphi_diff(ha);
-            Pp.h2db = dphi_diff(hb);
-            if (n >= r0 && n < r1 && out_lane) {
-                aHd.store(n, ha);
-                bHd.store(n, hb);
-                if (n == 1 && acc2) {
-                    A.acc_v[m] += hb;
-                    A.acc_vc[m] += hb * cw[4];
+
+        // Pm: slot of row j - D, P0: row j, Pp: row j + D (= j - 2D mod 3)
+        auto iter = [&](int j, Row2Regs& Pm, Row2Regs& P0, Row2Regs& Pp) {
+            // inputs loaded three iterations ago
+            Pp.f0a = P0.nfa;
+            Pp.f0b = P0.nfb;
+            const double ha0 = P0.nha, hb0 = P0.nhb;
+            issue(P0, j + 3 * D);
+            Pp.f0da = dphi_diff(Pp.f0a);
+            Pp.f0db = dphi_diff(Pp.f0b);
+
+            // W1: whole grid k -> k+1 at harmonic j
+            {
+                const double nd = static_cast<double>(j);
+                double At, Bt, ha, hb;
+                coupling(j, Pm.f0da, Pp.f0da, Pm.f0db, Pp.f0db, At, Bt);
+                op_T2(ha0, hb0, At, Bt, a0dt(j), nd * q[0], nd * q[2], nu, nu2, xi, ha, hb);
+                mask(j, ha, hb);
+                P0.h1a = ha;
+                P0.h1b = hb;
+                P0.h1da = dphi_diff(ha);
+                P0.h1db = dphi_diff(hb);
+                if constexpr (EDGE) {
+                    if (j == 1 && j >= r0 && j < r1 && out_lane && acc1) {
+                        A.acc_v[m] += hb;
+                        A.acc_vc[m] += hb * cw[2];
+                    }
                 }
             }
-        }
-        // F2: fractional grid k+3/2 -> k+5/2 at harmonic j-3
-        {
-            const int n = j - 3;
-            if (n >= r0 && n < r1) {
+            // F1: fractional grid k+1/2 -> k+3/2 at harmonic j - D
+            {
+                const int n = j - D;
                 const double nd = static_cast<double>(n);
-                double fa, fb;
-                op_T(P0.f1a, P0.f1b, c * (chi_of(n) * Pm.h2da - Pp.h2da),
-                     c * (Pp.h2db - Pm.h2db), s_of(n) * gdt, nd * q[3], nd * q[5], nu, xi, fa,
-                     fb);
-                if (out_lane) {
-                    aFd.store(n, fa);
-                    bFd.store(n, n >= 1 ? fb : 0.0);
+                double At, Bt, fa, fb;
+                // z^{k+1} at n - D = j - 2D (slot Pp) and n + D = j (slot P0)
+                coupling(n, Pp.h1da, P0.h1da, Pp.h1db, P0.h1db, At, Bt);
+                op_T2(Pm.f0a, Pm.f0b, At, Bt, a0dt(n), nd * q[1], nd * q[3], nu, nu2, xi, fa, fb);
+                mask(n, fa, fb);
+                Pm.f1a = fa;
+                Pm.f1b = fb;
+                Pm.f1da = dphi_diff(fa);
+                Pm.f1db = dphi_diff(fb);
+            }
+            // W2: whole grid k+1 -> k+2 at harmonic j - 2D
+            {
+                const int n = j - 2 * D;
+                const double nd = static_cast<double>(n);
+                double At, Bt, ha, hb;
+                // z^{k+3/2} at n - D = j - 3D (slot P0) and n + D = j - D (slot Pm)
+                coupling(n, P0.f1da, Pm.f1da, P0.f1db, Pm.f1db, At, Bt);
+                op_T2(Pp.h1a, Pp.h1b, At, Bt, a0dt(n), nd * q[2], nd * q[4], nu, nu2, xi, ha, hb);
+                mask(n, ha, hb);
+                Pp.h2da = dphi_diff(ha);
+                Pp.h2db = dphi_diff(hb);
+                if (n >= r0 && n < r1 && out_lane) {
+                    aHd.store(n, ha);
+                    bHd.store(n, hb);
+                    if constexpr (EDGE) {
+                        if (n == 1 && acc2) {
+                            A.acc_v[m] += hb;
+                            A.acc_vc[m] += hb * cw[4];
+                        }
+                    }
                 }
             }
+            // F2: fractional grid k+3/2 -> k+5/2 at harmonic j - 3D
+            {
+                const int n = j - 3 * D;
+                if (n >= r0 && n < r1) {
+                    const double nd = static_cast<double>(n);
+                    double At, Bt, fa, fb;
+                    // z^{k+2} at n - D = j - 4D (slot Pm) and n + D = j - 2D (slot Pp)
+                    coupling(n, Pm.h2da, Pp.h2da, Pm.h2db, Pp.h2db, At, Bt);
+                    op_T2(P0.f1a, P0.f1b, At, Bt, a0dt(n), nd * q[3], nd * q[5], nu, nu2, xi, fa, fb);
+                    if (out_lane) {
+                        aFd.store(n, fa);
+                        bFd.store(n, (!EDGE || n >= 1) ? fb : 0.0);
+                    }
+                }
+            }
+        };
+
+        // W1 rows jlo .. jhi (R + 6 iterations), padded to a multiple of 3 so the
+        // loop body is periodic in the slot rotation; padding iterations store nothing.
+        const int iters = (jhi - jlo + 1 + 2) / 3 * 3;
+        for (int i = 0; i < iters; i += 3) {
+            const int j = jfirst + D * i;
+            iter(j, S[0], S[1], S[2]);
+            iter(j + D, S[1], S[2], S[0]);
+            iter(j + 2 * D, S[2], S[0], S[1]);
         }
     };
-
-    // W1 rows jlo .. jhi (R + 6 iterations), padded to a multiple of 3 so the
-    // loop body is periodic in the slot rotation; padding iterations store nothing.
-    const int jend = jlo + (jhi - jlo + 1 + 2) / 3 * 3;
-    for (int j = jlo; j < jend; j += 3) {
-        iter(j, S[0], S[1], S[2]);
-        iter(j + 1, S[1], S[2], S[0]);
-        iter(j + 2, S[2], S[0], S[1]);
+    using Up = std::integral_constant<int, 1>;
+    using Down = std::integral_constant<int, -1>;
+    const bool up = ((r0 / A.R) & 1) == 0;
+    if (interior) {
+        if (up) run(std::false_type{}, Up{});
+        else run(std::false_type{}, Down{});
+    } else {
+        if (up) run(std::true_type{}, Up{});
+        else run(std::true_type{}, Down{});
     }
 }
 
