@@ -170,6 +170,92 @@ bte_status bte_tune(const bte_grid* grid, const bte_params* params, void* worksp
                     size_t workspace_bytes, void* hip_stream, int32_t kernel_form,
                     double target_ms, bte_tuning* best, double* best_us_per_step);
 
+/* ------------------------------------------------------------------------ */
+/* Batched parameter sweeps                                                  */
+/* ------------------------------------------------------------------------ */
+/* Many independent instances (each its own fields, temperature and phi_y
+   resolution) share the harmonic count, the phi_y box, dt and the precision.
+   Every instance starts from the equilibrium (or a warm start), runs whole
+   ac periods of T = 2 pi / omega, and stops when the absorption of two
+   consecutive periods differs by less than `tol` (after at least
+   `min_periods`), or after `max_periods`.  Period p covers the steps
+   round((p-1) T/dt) < k <= round(p T/dt); its absorption A_p and mean drift
+   velocity follow the Sec. 2 definitions over those steps.  One persistent,
+   graph-captured kernel launch runs the whole sweep: each workgroup takes the
+   next instance from a device work queue (largest expected cost first) and
+   advances it to convergence with the same per-cell arithmetic as the
+   single-instance solver. */
+
+typedef struct {
+    double E_dc, E_w, omega, B, mu;   /* as in bte_params; omega > 0 */
+    int32_t n_y;                       /* phi_y points of this instance, >= 3 */
+    int32_t reserved;                  /* must be 0 */
+} bte_instance;
+
+typedef struct {
+    int32_t n_x;            /* harmonics, shared, >= 2 */
+    int32_t precision;      /* bte_precision */
+    double phiy_min, phiy_max;
+    double dt;              /* time step (tau = 1) */
+    double alpha;           /* normalisation of f0 and v_dr, > 0 */
+    double tol;             /* absolute |A_p - A_{p-1}| threshold, > 0 */
+    int32_t min_periods;    /* >= 2 */
+    int32_t max_periods;    /* >= min_periods */
+} bte_batch_config;
+
+typedef struct {
+    int32_t kernel;         /* BTE_KERNEL_FUSED or BTE_KERNEL_FUSED2 */
+    int32_t rows_per_wave;  /* 1 .. 62 (58 for FUSED2) */
+    int32_t waves_per_group;/* wavefronts per workgroup: 2, 4 or 8 */
+    int32_t groups;         /* persistent workgroups (0: fill the GPU) */
+} bte_batch_tuning;
+
+typedef struct {
+    double absorption;      /* A_p of the last period run */
+    double v_avg;           /* mean drift velocity of that period */
+    double dA;              /* |A_p - A_{p-1}| of that period (0 if p = 1) */
+    int64_t steps;          /* whole steps taken */
+    int32_t periods;        /* periods completed */
+    int32_t converged;      /* 1 if dA < tol with p >= min_periods */
+    int32_t status;         /* BTE_OK, or BTE_EUNSTABLE for a non-finite observable */
+    int32_t reserved;
+} bte_result;
+
+typedef struct bte_batch bte_batch;
+
+/* Device bytes for a batch (instance tables, per-workgroup state slots sized
+   for the largest n_y, results), for the given tuning (NULL: default). */
+bte_status bte_batch_workspace_bytes(const bte_batch_config* cfg, int32_t n,
+                                     const bte_instance* inst, const bte_batch_tuning* tuning,
+                                     size_t* bytes);
+
+/* Create a batch of n instances.  Host tables are copied; the workspace
+   follows the same ownership rules as bte_create (NULL: library-allocated). */
+bte_status bte_batch_create(const bte_batch_config* cfg, int32_t n, const bte_instance* inst,
+                            const bte_batch_tuning* tuning, void* workspace,
+                            size_t workspace_bytes, void* hip_stream, bte_batch** out);
+
+/* Warm start: a device array of n x 64 x 128 floats (instance-major).  For
+   instance i, rows 0..31 hold a_n - a^(0)_n (n = 0..31) and rows 32..63 hold
+   b_n (n = 1..32), each sampled at 128 uniform points of the phi_y box and
+   divided by the envelope exp(-mu phi_y^2 / 2).  Instances start from the
+   linearly interpolated, re-enveloped state (harmonics >= 32 from the
+   equilibrium) instead of f0, at t = 0; the start-up half-step then derives
+   the fractional grid.  NULL restores the equilibrium start.  The array must
+   stay valid until the next bte_batch_run completes. */
+bte_status bte_batch_set_warm_start(bte_batch* b, const float* dev_coeffs);
+
+/* Queue the sweep (one graph launch); returns immediately. */
+bte_status bte_batch_run(bte_batch* b);
+
+/* Wait for the sweep and copy the n results out (synchronises). */
+bte_status bte_batch_results(bte_batch* b, bte_result* out);
+
+/* Tuning of the batch kernel (takes effect at the next run). */
+bte_status bte_batch_get_tuning(const bte_batch* b, bte_batch_tuning* t);
+
+void bte_batch_destroy(bte_batch* b);
+
 /* Destroy the handle; frees what the library allocated.  NULL is a no-op. */
 void bte_destroy(bte_solver* s);
 

@@ -52,6 +52,33 @@ class bte_obs(ctypes.Structure):
                 ("reserved", ctypes.c_int32)]
 
 
+class bte_instance(ctypes.Structure):
+    _fields_ = [("E_dc", ctypes.c_double), ("E_w", ctypes.c_double),
+                ("omega", ctypes.c_double), ("B", ctypes.c_double),
+                ("mu", ctypes.c_double), ("n_y", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class bte_batch_config(ctypes.Structure):
+    _fields_ = [("n_x", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("phiy_min", ctypes.c_double), ("phiy_max", ctypes.c_double),
+                ("dt", ctypes.c_double), ("alpha", ctypes.c_double),
+                ("tol", ctypes.c_double), ("min_periods", ctypes.c_int32),
+                ("max_periods", ctypes.c_int32)]
+
+
+class bte_batch_tuning(ctypes.Structure):
+    _fields_ = [("kernel", ctypes.c_int32), ("rows_per_wave", ctypes.c_int32),
+                ("waves_per_group", ctypes.c_int32), ("groups", ctypes.c_int32)]
+
+
+class bte_result(ctypes.Structure):
+    _fields_ = [("absorption", ctypes.c_double), ("v_avg", ctypes.c_double),
+                ("dA", ctypes.c_double), ("steps", ctypes.c_int64),
+                ("periods", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("status", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
 class BteError(RuntimeError):
     def __init__(self, status: int, func: str, msg: str):
         super().__init__(f"{func}: {STATUS_NAMES.get(status, status)}: {msg}")
@@ -77,6 +104,15 @@ def _load():
         "bte_get_tuning": ([vp, P(bte_tuning)], ctypes.c_int),
         "bte_tune": ([P(bte_grid), P(bte_params), vp, ctypes.c_size_t, vp, ctypes.c_int32,
                       ctypes.c_double, P(bte_tuning), dp], ctypes.c_int),
+        "bte_batch_workspace_bytes": ([P(bte_batch_config), ctypes.c_int32, P(bte_instance),
+                                       P(bte_batch_tuning), P(ctypes.c_size_t)], ctypes.c_int),
+        "bte_batch_create": ([P(bte_batch_config), ctypes.c_int32, P(bte_instance),
+                              P(bte_batch_tuning), vp, ctypes.c_size_t, vp, P(vp)], ctypes.c_int),
+        "bte_batch_set_warm_start": ([vp, vp], ctypes.c_int),
+        "bte_batch_run": ([vp], ctypes.c_int),
+        "bte_batch_results": ([vp, P(bte_result)], ctypes.c_int),
+        "bte_batch_get_tuning": ([vp, P(bte_batch_tuning)], ctypes.c_int),
+        "bte_batch_destroy": ([vp], None),
         "bte_destroy": ([vp], None),
         "bte_last_error": ([], ctypes.c_char_p),
         "bte_version": ([], ctypes.c_char_p),
@@ -175,6 +211,59 @@ def bte_tune(grid: bte_grid, params: bte_params, workspace_ptr: int, workspace_b
     return t, us.value
 
 
+def _inst_array(instances):
+    arr = (bte_instance * len(instances))()
+    for i, w in enumerate(instances):
+        arr[i] = bte_instance(float(w.E_dc), float(w.E_w), float(w.omega), float(w.B),
+                              float(w.mu), int(w.ny), 0)
+    return arr
+
+
+def bte_batch_workspace_bytes(cfg: bte_batch_config, instances, tuning=None) -> int:
+    arr = _inst_array(instances)
+    n = ctypes.c_size_t(0)
+    _check(_lib.bte_batch_workspace_bytes(ctypes.byref(cfg), len(arr), arr,
+                                          ctypes.byref(tuning) if tuning else None,
+                                          ctypes.byref(n)), "bte_batch_workspace_bytes")
+    return int(n.value)
+
+
+def bte_batch_create(cfg, instances, tuning, workspace_ptr, workspace_bytes, stream_ptr) -> int:
+    arr = _inst_array(instances)
+    h = ctypes.c_void_p(0)
+    _check(_lib.bte_batch_create(ctypes.byref(cfg), len(arr), arr,
+                                 ctypes.byref(tuning) if tuning else None,
+                                 ctypes.c_void_p(workspace_ptr or None), workspace_bytes,
+                                 ctypes.c_void_p(stream_ptr or None), ctypes.byref(h)),
+           "bte_batch_create")
+    return h.value
+
+
+def bte_batch_set_warm_start(h: int, dev_ptr: int):
+    _check(_lib.bte_batch_set_warm_start(ctypes.c_void_p(h), ctypes.c_void_p(dev_ptr or None)),
+           "bte_batch_set_warm_start")
+
+
+def bte_batch_run(h: int):
+    _check(_lib.bte_batch_run(ctypes.c_void_p(h)), "bte_batch_run")
+
+
+def bte_batch_results(h: int, n: int):
+    out = (bte_result * n)()
+    _check(_lib.bte_batch_results(ctypes.c_void_p(h), out), "bte_batch_results")
+    return out
+
+
+def bte_batch_get_tuning(h: int) -> bte_batch_tuning:
+    t = bte_batch_tuning()
+    _check(_lib.bte_batch_get_tuning(ctypes.c_void_p(h), ctypes.byref(t)), "bte_batch_get_tuning")
+    return t
+
+
+def bte_batch_destroy(h: int):
+    _lib.bte_batch_destroy(ctypes.c_void_p(h))
+
+
 def bte_destroy(h: int):
     _lib.bte_destroy(ctypes.c_void_p(h))
 
@@ -270,6 +359,106 @@ class Solver:
     def close(self):
         if getattr(self, "handle", None):
             bte_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def make_batch_config(n_x, phiy_min, phiy_max, dt, precision=BTE_FP64, alpha=1.0, tol=1e-6,
+                      min_periods=2, max_periods=200) -> bte_batch_config:
+    return bte_batch_config(int(n_x), int(precision), float(phiy_min), float(phiy_max),
+                            float(dt), float(alpha), float(tol), int(min_periods),
+                            int(max_periods))
+
+
+class Batch:
+    """A batched sweep of independent instances (see bte_batch_* in bte.h).
+
+    `instances` are objects with E_dc, E_w, omega, B, mu, ny (e.g. Workload).
+    With `tuning=None` the tile shape is picked by the autotuner on the
+    largest instance's grid (one- and two-step kernel forms only)."""
+
+    def __init__(self, cfg: bte_batch_config, instances, tuning=None, waves_per_group=8,
+                 groups=0, device="cuda", stream=None, autotune=True):
+        import torch
+        self.cfg = cfg
+        self.instances = list(instances)
+        self.n = len(self.instances)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        self.tune_us = None
+        if tuning is None:
+            tuning = bte_batch_tuning(BTE_KERNEL_FUSED2, 25, waves_per_group, groups)
+            if autotune:
+                big = max(self.instances, key=lambda w: w.ny)
+                g = make_grid(cfg.n_x, big.ny, cfg.phiy_min, cfg.phiy_max)
+                p = make_params(big.E_dc, big.E_w, big.omega, big.B, big.mu, cfg.dt,
+                                alpha=cfg.alpha, precision=cfg.precision)
+                nbytes = bte_workspace_bytes(g, p)
+                scratch = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+                ptr = (scratch.data_ptr() + 255) // 256 * 256
+                best = None
+                for form in (BTE_KERNEL_FUSED, BTE_KERNEL_FUSED2):
+                    t, us = bte_tune(g, p, ptr, nbytes, self.stream.cuda_stream, form, 1.0)
+                    if best is None or us < best[1]:
+                        best = (t, us)
+                del scratch
+                tuning.kernel = best[0].kernel
+                tuning.rows_per_wave = best[0].rows_per_wave
+                self.tune_us = best[1]
+        self.tuning = tuning
+        nbytes = bte_batch_workspace_bytes(cfg, self.instances, tuning)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        ptr = (self.workspace.data_ptr() + 255) // 256 * 256
+        self.handle = bte_batch_create(cfg, self.instances, tuning, ptr, nbytes,
+                                       self.stream.cuda_stream)
+        self._warm = None
+
+    def set_warm_start(self, coeffs):
+        """coeffs: a contiguous float32 CUDA tensor of shape (n, 64, 128), or None."""
+        if coeffs is None:
+            self._warm = None
+            bte_batch_set_warm_start(self.handle, 0)
+            return
+        assert coeffs.is_cuda and coeffs.dtype.is_floating_point and coeffs.is_contiguous()
+        assert tuple(coeffs.shape) == (self.n, 64, 128)
+        self._warm = coeffs
+        bte_batch_set_warm_start(self.handle, coeffs.data_ptr())
+
+    def run(self, wait=True, report_every=20.0, log=print):
+        """Queue the sweep; with wait=True block until it finishes, printing the
+        elapsed time every `report_every` seconds.  Returns wall seconds."""
+        import time
+        import torch
+        t0 = time.perf_counter()
+        done = torch.cuda.Event()
+        bte_batch_run(self.handle)
+        done.record(self.stream)
+        if not wait:
+            return 0.0
+        last = t0
+        while not done.query():
+            time.sleep(0.05)
+            now = time.perf_counter()
+            if log and now - last >= report_every:
+                log(f"  batch of {self.n} instances running: {now - t0:.0f} s", flush=True)
+                last = now
+        return time.perf_counter() - t0
+
+    def results(self):
+        r = bte_batch_results(self.handle, self.n)
+        return [dict(absorption=x.absorption, v_avg=x.v_avg, dA=x.dA, steps=x.steps,
+                     periods=x.periods, converged=x.converged, status=x.status) for x in r]
+
+    def get_tuning(self) -> bte_batch_tuning:
+        return bte_batch_get_tuning(self.handle)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            bte_batch_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

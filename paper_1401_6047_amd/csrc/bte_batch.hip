@@ -1,0 +1,645 @@
+// Batched parameter sweep: one persistent, graph-captured launch runs many
+// independent instances of the superlattice BTE to per-period convergence.
+//
+// Each workgroup owns a state slot (two ping-pong sets of the four planes,
+// sized for the largest N_y of the batch, plus the phi_y envelope and the
+// per-phi_y window sums) and loops: take the next instance from a device work
+// queue, initialise it (equilibrium or warm start, then the start-up
+// half-step), run whole ac periods with the one- or two-step tile kernels and
+// a workgroup barrier between passes, reduce the period's drift velocity and
+// absorption, and stop on convergence of the period-to-period absorption.
+// The tiles of one pass are spread over the workgroup's wavefronts; the
+// per-cell arithmetic is the single-instance solver's (same device code).
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/bte.h"
+#include "bte_device.h"
+
+namespace bte {
+namespace {
+
+using namespace detail;
+
+constexpr int kMaxWavesPerGroup = 8;
+constexpr int kWarmRows = 64;       // warm-start coefficient rows (32 a + 32 b)
+constexpr int kWarmCols = 128;      // warm-start phi_y samples
+constexpr int kWarmHarmonics = 32;
+
+// Per-instance constants, prepared on the host.
+struct BatchInst {
+    double E_dc, E_w, omega, B, mu;
+    double dphi;          // phi_y spacing of this instance
+    double period_steps;  // T / dt
+    double two_over_ratio1;   // 2 I_0(mu) / I_1(mu)
+    double v_norm;        // pi sqrt(alpha) dphi: v_dr = v_norm sum_m b_1(m)
+    int32_t ny;
+    int32_t pad;
+};
+
+template <typename T>
+struct BatchArgs {
+    const BatchInst* inst;
+    const double* s_all;      // [n][nx] source coefficients
+    const int32_t* order;     // work order (instance indices)
+    const float* warm;        // [n][64][128] or null
+    bte_result* results;
+    int32_t* queue;           // next-instance counter
+    char* slots;              // per-workgroup state slots
+    size_t slot_bytes;
+    size_t plane_bytes;       // bytes of one padded plane (256-aligned)
+    size_t off_g, off_accv, off_accvc;   // offsets inside a slot
+    Consts base;              // nx, ld, dt, phimin, nu, xi (per-instance fields filled in-kernel)
+    int n;
+    int R;                    // harmonics per wave
+    int form;                 // BTE_KERNEL_FUSED or BTE_KERNEL_FUSED2
+    double tol;
+    int min_periods, max_periods;
+};
+
+__global__ void k_batch_reset(int32_t* queue)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) queue[0] = 0;
+}
+
+// Values every lane agrees on, made provably uniform (scalar registers).
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ double uni(double v)
+{
+    const int lo = __builtin_amdgcn_readfirstlane(__double2loint(v));
+    const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
+
+// Deterministic workgroup sum of two values (fixed order).
+__device__ __forceinline__ void group_sum2(double& x, double& y, double* red, int nwaves)
+{
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        x += __shfl_down(x, o);
+        y += __shfl_down(y, o);
+    }
+    if (lane == 0) {
+        red[2 * wave] = x;
+        red[2 * wave + 1] = y;
+    }
+    __syncthreads();
+    double sx = 0, sy = 0;
+    for (int w = 0; w < nwaves; ++w) {
+        sx += red[2 * w];
+        sy += red[2 * w + 1];
+    }
+    x = sx;
+    y = sy;
+    __syncthreads();
+}
+
+template <typename T>
+__global__ __launch_bounds__(kMaxWavesPerGroup * kWave) void k_batch(BatchArgs<T> B)
+{
+    __shared__ int s_q;
+    __shared__ double s_red[2 * kMaxWavesPerGroup];
+    __shared__ double s_tab[kMaxWavesPerGroup][kWave];
+    const int nwaves = blockDim.x / kWave;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    char* slot = B.slots + static_cast<size_t>(blockIdx.x) * B.slot_bytes;
+    double* g_m = reinterpret_cast<double*>(slot + B.off_g);
+    double* acc_v = reinterpret_cast<double*>(slot + B.off_accv);
+    double* acc_vc = reinterpret_cast<double*>(slot + B.off_accvc);
+    auto plane = [&](int set, int which) {
+        return reinterpret_cast<T*>(slot + (set * 4 + which) * B.plane_bytes);   // physical base
+    };
+    auto planes = [&](int set) {
+        return Planes<T>{plane(set, 0), plane(set, 1), plane(set, 2), plane(set, 3)};
+    };
+    const int nx = B.base.nx, ld = B.base.ld;
+    const int rows = nx + 2 * kPadRows;
+
+    while (true) {
+        __syncthreads();
+        if (threadIdx.x == 0) s_q = atomicAdd(&B.queue[0], 1);
+        __syncthreads();
+        const int q = uni(s_q);
+        if (q >= B.n) break;
+        const int idx = uni(B.order[q]);
+        BatchInst I = B.inst[idx];
+        I.E_dc = uni(I.E_dc);
+        I.E_w = uni(I.E_w);
+        I.omega = uni(I.omega);
+        I.B = uni(I.B);
+        I.mu = uni(I.mu);
+        I.dphi = uni(I.dphi);
+        I.period_steps = uni(I.period_steps);
+        I.two_over_ratio1 = uni(I.two_over_ratio1);
+        I.v_norm = uni(I.v_norm);
+        I.ny = uni(I.ny);
+        Consts cs = B.base;
+        cs.ny = I.ny;
+        cs.dphi = I.dphi;
+        cs.B = I.B;
+        cs.E_dc = I.E_dc;
+        cs.E_w = I.E_w;
+        cs.omega = I.omega;
+        cs.c_full = I.B * cs.dt / (4.0 * I.dphi);
+        const double* s_n = B.s_all + static_cast<size_t>(idx) * nx;
+        const float* warm = B.warm ? B.warm + static_cast<size_t>(idx) * kWarmRows * kWarmCols : nullptr;
+
+        // ---- initial state: every cell of all eight planes (clears what the
+        // previous instance left), whole and fractional grid of set 0 = z^0
+        for (int m = threadIdx.x; m < ld; m += blockDim.x) {
+            const double phi = cs.phimin + m * cs.dphi;
+            g_m[m] = (m < I.ny) ? exp(-0.5 * I.mu * phi * phi) : 0.0;
+        }
+        __syncthreads();
+        const double box = (I.ny - 1) * I.dphi;
+        for (int64_t e = threadIdx.x; e < static_cast<int64_t>(rows) * ld; e += blockDim.x) {
+            const int row = static_cast<int>(e / ld), col = static_cast<int>(e - static_cast<int64_t>(row) * ld);
+            const int n = row - kPadRows, m = col - kPadCols;
+            double a = 0.0, b = 0.0;
+            if (n >= 0 && n < nx && m >= 0 && m < I.ny) {
+                const double g = g_m[m];
+                a = s_n[n] * g;
+                if (warm && n < kWarmHarmonics) {
+                    // linear interpolation of the coefficient rows in phi_y
+                    const double u = (m * I.dphi) / box * (kWarmCols - 1);
+                    const int j0 = min(static_cast<int>(u), kWarmCols - 2);
+                    const double w = u - j0;
+                    const float* ra = warm + n * kWarmCols;
+                    a += g * ((1.0 - w) * ra[j0] + w * ra[j0 + 1]);
+                    if (n >= 1) {
+                        const float* rb = warm + (kWarmHarmonics + n - 1) * kWarmCols;
+                        b = g * ((1.0 - w) * rb[j0] + w * rb[j0 + 1]);
+                    }
+                }
+            }
+            const T ta = static_cast<T>(a), tb = static_cast<T>(b), zero = static_cast<T>(0.0);
+            plane(0, 0)[e] = ta;
+            plane(0, 1)[e] = tb;
+            plane(0, 2)[e] = ta;
+            plane(0, 3)[e] = tb;
+            plane(1, 0)[e] = zero;
+            plane(1, 1)[e] = zero;
+            plane(1, 2)[e] = zero;
+            plane(1, 3)[e] = zero;
+        }
+        __syncthreads();
+        const uint32_t salt = 16u * static_cast<uint32_t>(idx + 1);
+
+        // ---- start-up half-step: z^{1/2} = T_{dt/2}(z^0; coupling from z^0)
+        {
+            HalfEnv<T> E{};
+            E.xa = plane(0, 2);
+            E.xb = plane(0, 3);
+            E.ya = plane(0, 0);
+            E.yb = plane(0, 1);
+            E.s_n = s_n;
+            E.g_m = g_m;
+            E.acc_v = acc_v;
+            E.acc_vc = acc_vc;
+            E.cs = cs;
+            E.h = 0.5 * cs.dt;
+            E.off0 = 0;
+            E.off1 = 1;
+            E.k = 0;
+            E.acc1 = false;
+            E.salt = salt;
+            E.R = min(B.R, kWave);
+            E.nchunks = (nx + E.R - 1) / E.R;
+            const int ntiles = E.nchunks * ((I.ny + kHalfCols - 1) / kHalfCols);
+            for (int t = wave; t < ntiles; t += nwaves) half_tile<T>(E, t);
+        }
+        __syncthreads();
+
+        // ---- whole ac periods until the absorption settles
+        TileEnv<T> E{};
+        E.s_n = s_n;
+        E.g_m = g_m;
+        E.acc_v = acc_v;
+        E.acc_vc = acc_vc;
+        E.cs = cs;
+        E.acc1 = true;
+        E.acc2 = true;
+        E.salt = salt;
+        const int R1 = min(B.R, kWave - 2), R2 = min(B.R, kWave - 6);
+        const int n1 = (nx + R1 - 1) / R1, n2 = (nx + R2 - 1) / R2;
+        const int tiles1 = n1 * ((I.ny + kFusedCols - 1) / kFusedCols);
+        const int tiles2 = n2 * ((I.ny + kFused2Cols - 1) / kFused2Cols);
+        int64_t k = 0;
+        int cur = 0, p = 0, converged = 0;
+        int32_t status = BTE_OK;
+        double A_prev = 0.0, A_p = 0.0, v_p = 0.0, dA = 0.0;
+        while (true) {
+            ++p;
+            const int64_t pstart = k;
+            const int64_t pend = static_cast<int64_t>(rint(p * I.period_steps));
+            for (int m = threadIdx.x; m < I.ny; m += blockDim.x) {
+                acc_v[m] = 0.0;
+                acc_vc[m] = 0.0;
+            }
+            __syncthreads();
+            while (k < pend) {
+                E.src = planes(cur);
+                E.dst = planes(1 - cur);
+                E.k = k;
+                if (B.form == BTE_KERNEL_FUSED2 && pend - k >= 2) {
+                    E.R = R2;
+                    E.nchunks = n2;
+                    for (int t = wave; t < tiles2; t += nwaves) fused2_tile<T>(E, t, &s_tab[wave][0]);
+                    k += 2;
+                } else {
+                    E.R = R1;
+                    E.nchunks = n1;
+                    for (int t = wave; t < tiles1; t += nwaves) fused_tile<T>(E, t);
+                    k += 1;
+                }
+                cur = 1 - cur;
+                __syncthreads();
+            }
+            // period reduction over phi_y (fixed order)
+            double sv = 0.0, svc = 0.0;
+            for (int m = threadIdx.x; m < I.ny; m += blockDim.x) {
+                sv += acc_v[m];
+                svc += acc_vc[m];
+            }
+            group_sum2(sv, svc, s_red, nwaves);
+            const double K = static_cast<double>(pend - pstart);
+            v_p = I.v_norm * sv / K;
+            A_p = I.two_over_ratio1 * I.v_norm * svc / K;
+            dA = (p > 1) ? fabs(A_p - A_prev) : 0.0;
+            if (!isfinite(A_p) || !isfinite(v_p)) {
+                status = BTE_EUNSTABLE;
+                break;
+            }
+            if (p >= B.min_periods && p > 1 && dA < B.tol) {
+                converged = 1;
+                break;
+            }
+            if (p >= B.max_periods) break;
+            A_prev = A_p;
+        }
+        if (threadIdx.x == 0) {
+            bte_result r{};
+            r.absorption = A_p;
+            r.v_avg = v_p;
+            r.dA = dA;
+            r.steps = k;
+            r.periods = p;
+            r.converged = converged;
+            r.status = status;
+            B.results[idx] = r;
+        }
+    }
+}
+
+}  // namespace
+}  // namespace bte
+
+// ---------------------------------------------------------------------------
+// host runtime
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+
+struct BatchLayout {
+    int ld = 0;
+    size_t elem = 8;
+    size_t plane_bytes = 0, slot_bytes = 0;
+    size_t off_g = 0, off_accv = 0, off_accvc = 0;
+    size_t off_inst = 0, off_s = 0, off_order = 0, off_results = 0, off_queue = 0, off_slots = 0;
+    size_t total = 0;
+    int groups = 0;
+};
+
+bte_batch_tuning default_batch_tuning()
+{
+    bte_batch_tuning t{};
+    t.kernel = BTE_KERNEL_FUSED2;
+    t.rows_per_wave = 25;
+    t.waves_per_group = 8;
+    t.groups = 0;
+    return t;
+}
+
+int device_cus()
+{
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess)
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    return cus > 0 ? cus : 256;
+}
+
+BatchLayout batch_layout(const bte_batch_config& c, int n, int ny_max, const bte_batch_tuning& t)
+{
+    using namespace bte;
+    BatchLayout L;
+    int need = std::max({col_extent(ny_max, kHalfCols, 1), col_extent(ny_max, kFusedCols, 2),
+                         col_extent(ny_max, kFused2Cols, 4), ny_max + 2 * kPadCols});
+    L.ld = (need + 63) / 64 * 64;
+    L.elem = c.precision == BTE_FP32_BULK ? 4 : 8;
+    L.plane_bytes = align_up(static_cast<size_t>(c.n_x + 2 * kPadRows) * L.ld * L.elem);
+    size_t o = 8 * L.plane_bytes;
+    L.off_g = o; o += align_up(sizeof(double) * L.ld);
+    L.off_accv = o; o += align_up(sizeof(double) * L.ld);
+    L.off_accvc = o; o += align_up(sizeof(double) * L.ld);
+    L.slot_bytes = o;
+    L.groups = t.groups > 0 ? t.groups : device_cus() * std::max(1, kMaxWavesPerGroup / t.waves_per_group);
+    size_t g = 0;
+    L.off_queue = g; g += align_up(64);
+    L.off_inst = g; g += align_up(sizeof(bte::BatchInst) * n);
+    L.off_s = g; g += align_up(sizeof(double) * static_cast<size_t>(n) * c.n_x);
+    L.off_order = g; g += align_up(sizeof(int32_t) * n);
+    L.off_results = g; g += align_up(sizeof(bte_result) * n);
+    L.off_slots = g; g += L.slot_bytes * L.groups;
+    L.total = g;
+    return L;
+}
+
+bte_status bfail(bte_status st, const std::string& msg)
+{
+    bte::set_last_error(msg.c_str());
+    return st;
+}
+
+bte_status validate_batch(const bte_batch_config* c, int n, const bte_instance* in,
+                          const bte_batch_tuning* t, int* ny_max)
+{
+    if (!c || !in || n <= 0) return bfail(BTE_EINVAL, "config, instances and n > 0 required");
+    if (c->n_x < 2 || c->n_x > 4096) return bfail(BTE_EINVAL, "n_x must be in 2..4096");
+    if (!(c->phiy_max > c->phiy_min) || !std::isfinite(c->phiy_min) || !std::isfinite(c->phiy_max))
+        return bfail(BTE_EINVAL, "need finite phiy_min < phiy_max");
+    if (!(c->dt > 0) || !(c->alpha > 0) || !(c->tol > 0))
+        return bfail(BTE_EINVAL, "dt, alpha and tol must be > 0");
+    if (c->precision != BTE_FP64 && c->precision != BTE_FP32_BULK)
+        return bfail(BTE_EINVAL, "unknown precision");
+    if (c->min_periods < 2 || c->max_periods < c->min_periods)
+        return bfail(BTE_EINVAL, "need 2 <= min_periods <= max_periods");
+    if (t) {
+        if (t->kernel != BTE_KERNEL_FUSED && t->kernel != BTE_KERNEL_FUSED2)
+            return bfail(BTE_EINVAL, "batch kernel must be FUSED or FUSED2");
+        if (t->rows_per_wave < 1 || t->rows_per_wave > bte::kWave - 2)
+            return bfail(BTE_EINVAL, "rows_per_wave out of range");
+        if (t->waves_per_group != 2 && t->waves_per_group != 4 && t->waves_per_group != 8)
+            return bfail(BTE_EINVAL, "waves_per_group must be 2, 4 or 8");
+        if (t->groups < 0) return bfail(BTE_EINVAL, "groups must be >= 0");
+    }
+    int mx = 0;
+    for (int i = 0; i < n; ++i) {
+        const bte_instance& I = in[i];
+        const double v[] = {I.E_dc, I.E_w, I.omega, I.B, I.mu};
+        for (double x : v)
+            if (!std::isfinite(x)) return bfail(BTE_EINVAL, "instance " + std::to_string(i) + ": non-finite parameter");
+        if (!(I.omega > 0) || !(I.mu > 0) || I.n_y < 3 || I.n_y > (1 << 20) || I.reserved != 0)
+            return bfail(BTE_EINVAL, "instance " + std::to_string(i) + ": need omega > 0, mu > 0, n_y >= 3");
+        const double dphi = (c->phiy_max - c->phiy_min) / (I.n_y - 1);
+        if (!(c->dt * std::fabs(I.B) / (2.0 * dphi) < 1.0))
+            return bfail(BTE_EINVAL, "instance " + std::to_string(i) + ": leap-frog bound dt |B| / (2 dphi) >= 1");
+        mx = std::max(mx, I.n_y);
+    }
+    *ny_max = mx;
+    return BTE_OK;
+}
+
+}  // namespace
+
+struct bte_batch {
+    bte_batch_config cfg{};
+    bte_batch_tuning tune{};
+    int n = 0;
+    hipStream_t stream = nullptr;
+    hipStream_t capture_stream = nullptr;
+    char* ws = nullptr;
+    bool owns = false;
+    BatchLayout L;
+    const float* warm = nullptr;
+    hipGraphExec_t graph = nullptr;
+    const float* graph_warm = nullptr;
+    bool ran = false;
+};
+
+namespace {
+
+template <typename T>
+hipError_t capture_batch(bte_batch* b)
+{
+    bte::BatchArgs<T> A{};
+    char* ws = b->ws;
+    A.inst = reinterpret_cast<const bte::BatchInst*>(ws + b->L.off_inst);
+    A.s_all = reinterpret_cast<const double*>(ws + b->L.off_s);
+    A.order = reinterpret_cast<const int32_t*>(ws + b->L.off_order);
+    A.warm = b->warm;
+    A.results = reinterpret_cast<bte_result*>(ws + b->L.off_results);
+    A.queue = reinterpret_cast<int32_t*>(ws + b->L.off_queue);
+    A.slots = ws + b->L.off_slots;
+    A.slot_bytes = b->L.slot_bytes;
+    A.plane_bytes = b->L.plane_bytes;
+    A.off_g = b->L.off_g;
+    A.off_accv = b->L.off_accv;
+    A.off_accvc = b->L.off_accvc;
+    bte::Consts& c = A.base;
+    c.nx = b->cfg.n_x;
+    c.ld = b->L.ld;
+    c.dt = b->cfg.dt;
+    c.half_dt = 0.5 * b->cfg.dt;
+    c.phimin = b->cfg.phiy_min;
+    c.nu = 1.0 + 0.5 * b->cfg.dt;
+    c.xi = 1.0 - 0.5 * b->cfg.dt;
+    A.n = b->n;
+    A.R = b->tune.rows_per_wave;
+    A.form = b->tune.kernel;
+    A.tol = b->cfg.tol;
+    A.min_periods = b->cfg.min_periods;
+    A.max_periods = b->cfg.max_periods;
+    hipLaunchKernelGGL(bte::k_batch_reset, dim3(1), dim3(64), 0, b->capture_stream, A.queue);
+    hipLaunchKernelGGL(bte::k_batch<T>, dim3(b->L.groups), dim3(b->tune.waves_per_group * bte::kWave),
+                       0, b->capture_stream, A);
+    return hipGetLastError();
+}
+
+bte_status build_batch_graph(bte_batch* b)
+{
+    if (b->graph) {
+        (void)hipGraphExecDestroy(b->graph);
+        b->graph = nullptr;
+    }
+    if (!b->capture_stream) {
+        hipError_t e = hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking);
+        if (e != hipSuccess) return bfail(BTE_EDEVICE, std::string("stream: ") + hipGetErrorString(e));
+    }
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return bfail(BTE_EDEVICE, std::string("capture: ") + hipGetErrorString(e));
+    hipError_t e1 = b->cfg.precision == BTE_FP32_BULK ? capture_batch<float>(b) : capture_batch<double>(b);
+    hipError_t e2 = hipStreamEndCapture(b->capture_stream, &g);
+    if (e1 != hipSuccess || e2 != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return bfail(BTE_EDEVICE, std::string("batch capture: ") + hipGetErrorString(e1 != hipSuccess ? e1 : e2));
+    }
+    e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return bfail(BTE_EDEVICE, std::string("instantiate: ") + hipGetErrorString(e));
+    b->graph_warm = b->warm;
+    return BTE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+bte_status bte_batch_workspace_bytes(const bte_batch_config* cfg, int32_t n,
+                                     const bte_instance* inst, const bte_batch_tuning* tuning,
+                                     size_t* bytes)
+{
+    int ny_max = 0;
+    bte_status st = validate_batch(cfg, n, inst, tuning, &ny_max);
+    if (st != BTE_OK) return st;
+    if (!bytes) return bfail(BTE_EINVAL, "bytes must not be NULL");
+    const bte_batch_tuning t = tuning ? *tuning : default_batch_tuning();
+    *bytes = batch_layout(*cfg, n, ny_max, t).total;
+    return BTE_OK;
+}
+
+bte_status bte_batch_create(const bte_batch_config* cfg, int32_t n, const bte_instance* inst,
+                            const bte_batch_tuning* tuning, void* workspace,
+                            size_t workspace_bytes, void* hip_stream, bte_batch** out)
+{
+    if (!out) return bfail(BTE_EINVAL, "out must not be NULL");
+    *out = nullptr;
+    int ny_max = 0;
+    bte_status st = validate_batch(cfg, n, inst, tuning, &ny_max);
+    if (st != BTE_OK) return st;
+    const bte_batch_tuning t = tuning ? *tuning : default_batch_tuning();
+    BatchLayout L = batch_layout(*cfg, n, ny_max, t);
+    if (static_cast<double>(L.plane_bytes) >= 2147483648.0)
+        return bfail(BTE_EINVAL, "grid too large: one state plane must stay below 2 GiB");
+    if (workspace && workspace_bytes < L.total)
+        return bfail(BTE_ENOMEM, "workspace too small: need " + std::to_string(L.total) + " bytes");
+    if (workspace && reinterpret_cast<uintptr_t>(workspace) % kAlign)
+        return bfail(BTE_EINVAL, "workspace must be 256-byte aligned");
+
+    bte_batch* b = new bte_batch();
+    b->cfg = *cfg;
+    b->tune = t;
+    b->n = n;
+    b->stream = static_cast<hipStream_t>(hip_stream);
+    b->L = L;
+    if (workspace) {
+        b->ws = static_cast<char*>(workspace);
+    } else {
+        hipError_t e = hipMalloc(reinterpret_cast<void**>(&b->ws), L.total);
+        if (e != hipSuccess) {
+            delete b;
+            return bfail(BTE_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+        }
+        b->owns = true;
+    }
+
+    // per-instance tables
+    std::vector<bte::BatchInst> I(n);
+    std::vector<double> S(static_cast<size_t>(n) * cfg->n_x);
+    std::vector<double> cost(n);
+    for (int i = 0; i < n; ++i) {
+        const bte_instance& x = inst[i];
+        bte::BatchInst& y = I[i];
+        y.E_dc = x.E_dc;
+        y.E_w = x.E_w;
+        y.omega = x.omega;
+        y.B = x.B;
+        y.mu = x.mu;
+        y.ny = x.n_y;
+        y.dphi = (cfg->phiy_max - cfg->phiy_min) / (x.n_y - 1);
+        y.period_steps = 2.0 * kPi / (x.omega * cfg->dt);
+        std::vector<double> r = bte::bessel_ratio_table(x.mu, cfg->n_x);
+        y.two_over_ratio1 = 2.0 / r[1];
+        y.v_norm = kPi * std::sqrt(cfg->alpha) * y.dphi;
+        const double norm = std::sqrt(x.mu / (2.0 * kPi * cfg->alpha)) / kPi;
+        for (int k = 0; k < cfg->n_x; ++k)
+            S[static_cast<size_t>(i) * cfg->n_x + k] = (k == 0 ? 0.5 : 1.0) * r[k] * norm;
+        // expected cost: cells x steps of the first min_periods periods or ~14
+        // relaxation times, whichever is longer
+        const double t_run = std::max(cfg->min_periods * 2.0 * kPi / x.omega, 14.0);
+        cost[i] = static_cast<double>(x.n_y) * cfg->n_x * t_run / cfg->dt;
+    }
+    std::vector<int32_t> order(n);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return cost[a] > cost[c]; });
+
+    hipError_t e = hipMemcpyAsync(b->ws + L.off_inst, I.data(), sizeof(bte::BatchInst) * n,
+                                  hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->ws + L.off_s, S.data(), sizeof(double) * S.size(), hipMemcpyHostToDevice,
+                           b->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->ws + L.off_order, order.data(), sizeof(int32_t) * n,
+                           hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(b->ws + L.off_results, 0, sizeof(bte_result) * n, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) {
+        bte_batch_destroy(b);
+        return bfail(BTE_EDEVICE, std::string("batch tables: ") + hipGetErrorString(e));
+    }
+    *out = b;
+    return BTE_OK;
+}
+
+bte_status bte_batch_set_warm_start(bte_batch* b, const float* dev_coeffs)
+{
+    if (!b) return bfail(BTE_EINVAL, "batch is NULL");
+    b->warm = dev_coeffs;
+    return BTE_OK;
+}
+
+bte_status bte_batch_run(bte_batch* b)
+{
+    if (!b) return bfail(BTE_EINVAL, "batch is NULL");
+    if (!b->graph || b->graph_warm != b->warm) {
+        bte_status st = build_batch_graph(b);
+        if (st != BTE_OK) return st;
+    }
+    hipError_t e = hipGraphLaunch(b->graph, b->stream);
+    if (e != hipSuccess) return bfail(BTE_EDEVICE, std::string("graph launch: ") + hipGetErrorString(e));
+    b->ran = true;
+    return BTE_OK;
+}
+
+bte_status bte_batch_results(bte_batch* b, bte_result* out)
+{
+    if (!b || !out) return bfail(BTE_EINVAL, "batch and out must not be NULL");
+    if (!b->ran) return bfail(BTE_ESTATE, "bte_batch_run has not been called");
+    hipError_t e = hipMemcpyAsync(out, b->ws + b->L.off_results, sizeof(bte_result) * b->n,
+                                  hipMemcpyDeviceToHost, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return bfail(BTE_EDEVICE, std::string("results: ") + hipGetErrorString(e));
+    return BTE_OK;
+}
+
+bte_status bte_batch_get_tuning(const bte_batch* b, bte_batch_tuning* t)
+{
+    if (!b || !t) return bfail(BTE_EINVAL, "batch and tuning must not be NULL");
+    *t = b->tune;
+    t->groups = b->L.groups;
+    return BTE_OK;
+}
+
+void bte_batch_destroy(bte_batch* b)
+{
+    if (!b) return;
+    (void)hipStreamSynchronize(b->stream);
+    if (b->graph) (void)hipGraphExecDestroy(b->graph);
+    if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
+    if (b->owns && b->ws) (void)hipFree(b->ws);
+    delete b;
+}
+
+}  // extern "C"

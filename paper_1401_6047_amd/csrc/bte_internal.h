@@ -6,6 +6,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <vector>
 
 namespace bte {
 
@@ -67,6 +68,12 @@ struct Shape {
     int rows_per_wave;
     int waves_per_block;
 };
+
+// ---- host helpers (bte_solver.hip) -----------------------------------------
+// Message returned by bte_last_error() on this thread.
+void set_last_error(const char* msg);
+// I_n(mu)/I_0(mu) for n = 0..nmax.
+std::vector<double> bessel_ratio_table(double mu, int nmax);
 
 // ---- launchers (bte_kernels.hip) ------------------------------------------
 // All pointers to planes point at logical (n = 0, m = 0).

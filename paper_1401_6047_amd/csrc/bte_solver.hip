@@ -23,8 +23,40 @@
 #include "bte_internal.h"
 
 namespace {
-
 thread_local std::string g_last_error;
+}  // namespace
+
+namespace bte {
+
+void set_last_error(const char* msg) { g_last_error = msg; }
+
+// I_n(mu)/I_0(mu) for n = 0..nmax.  The ratios r_n = I_n/I_{n-1} satisfy
+// r_n = 1/(2n/mu + r_{n+1}) (the three-term recurrence divided through);
+// iterating that continued fraction downward from far above nmax converges
+// to the minimal solution, and I_n/I_0 is the running product of r_1..r_n.
+std::vector<double> bessel_ratio_table(double mu, int nmax)
+{
+    int top = nmax + 64 + static_cast<int>(4.0 * std::sqrt(mu + 1.0) + mu);
+    std::vector<double> r(top + 2, 0.0);
+    double next = 0.0;
+    for (int n = top; n >= 1; --n) {
+        next = 1.0 / (2.0 * n / mu + next);
+        r[n] = next;
+    }
+    std::vector<double> out(nmax + 1);
+    out[0] = 1.0;
+    double p = 1.0;
+    for (int n = 1; n <= nmax; ++n) {
+        p *= r[n];
+        out[n] = p;
+    }
+    return out;
+}
+
+}  // namespace bte
+
+namespace {
+using bte::bessel_ratio_table;
 
 bte_status fail(bte_status st, const char* fmt, ...)
 {
@@ -51,29 +83,6 @@ constexpr int kMaxRowsPerWave = bte::kWave - 2;
 constexpr size_t kAlign = 256;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
-
-// I_n(mu)/I_0(mu) for n = 0..nmax.  The ratios r_n = I_n/I_{n-1} satisfy
-// r_n = 1/(2n/mu + r_{n+1}) (the three-term recurrence divided through);
-// iterating that continued fraction downward from far above nmax converges
-// to the minimal solution, and I_n/I_0 is the running product of r_1..r_n.
-std::vector<double> bessel_ratio_table(double mu, int nmax)
-{
-    int top = nmax + 64 + static_cast<int>(4.0 * std::sqrt(mu + 1.0) + mu);
-    std::vector<double> r(top + 2, 0.0);
-    double next = 0.0;
-    for (int n = top; n >= 1; --n) {
-        next = 1.0 / (2.0 * n / mu + next);
-        r[n] = next;
-    }
-    std::vector<double> out(nmax + 1);
-    out[0] = 1.0;
-    double p = 1.0;
-    for (int n = 1; n <= nmax; ++n) {
-        p *= r[n];
-        out[n] = p;
-    }
-    return out;
-}
 
 struct Layout {
     int ld = 0;             // row stride of a plane, elements

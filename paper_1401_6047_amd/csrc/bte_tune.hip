@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "../../include/bte.h"
+#include "bte_internal.h"
 
 namespace {
 
@@ -47,8 +48,14 @@ extern "C" bte_status bte_tune(const bte_grid* grid, const bte_params* params, v
                                size_t workspace_bytes, void* hip_stream, int32_t kernel_form,
                                double target_ms, bte_tuning* best, double* best_us_per_step)
 {
-    if (!best) return BTE_EINVAL;
-    if (kernel_form < -1 || kernel_form > BTE_KERNEL_FUSED2) return BTE_EINVAL;
+    if (!best) {
+        bte::set_last_error("best must not be NULL");
+        return BTE_EINVAL;
+    }
+    if (kernel_form < -1 || kernel_form > BTE_KERNEL_FUSED2) {
+        bte::set_last_error("kernel_form must be -1 or a bte_kernel value");
+        return BTE_EINVAL;
+    }
     bte_solver* s = nullptr;
     bte_status rc = bte_create(grid, params, workspace, workspace_bytes, hip_stream, &s);
     if (rc != BTE_OK) return rc;
@@ -56,6 +63,7 @@ extern "C" bte_status bte_tune(const bte_grid* grid, const bte_params* params, v
     EventPair ev;
     if (hipEventCreate(&ev.a) != hipSuccess || hipEventCreate(&ev.b) != hipSuccess) {
         bte_destroy(s);
+        bte::set_last_error("hipEventCreate failed");
         return BTE_EDEVICE;
     }
     if (!(target_ms > 0)) target_ms = 2.0;
@@ -69,6 +77,7 @@ extern "C" bte_status bte_tune(const bte_grid* grid, const bte_params* params, v
     double us0 = time_steps(s, base, std::max(G, 8), st, ev);
     if (us0 <= 0) {
         bte_destroy(s);
+        bte::set_last_error("timing the default shape failed");
         return BTE_EDEVICE;
     }
     int n = static_cast<int>(target_ms * 1e3 / us0);
@@ -99,7 +108,10 @@ extern "C" bte_status bte_tune(const bte_grid* grid, const bte_params* params, v
         }
     }
     bte_destroy(s);
-    if (win_us <= 0) return BTE_EDEVICE;
+    if (win_us <= 0) {
+        bte::set_last_error("no candidate shape could be timed");
+        return BTE_EDEVICE;
+    }
     *best = win;
     if (best_us_per_step) *best_us_per_step = win_us;
     return BTE_OK;

@@ -141,3 +141,18 @@ def sweep_draws(n: int, seed: int = SWEEP_SEED, nx: int = 128, dt: float = 1e-4)
                             phiy_min=-10.0, phiy_max=10.0, E_dc=E_dc, E_w=0.1,
                             omega=omega, B=B, mu=mu, dt=dt))
     return out
+
+
+def small_sweep_draws(n: int, seed: int, nx: int = 16, ny_choices=(41, 61, 81),
+                      phi: float = 6.0, dt: float = 2e-3):
+    """Seeded small instances with uneven N_y for batch parity tests (the same
+    draw shape as the sweep, on grids the CPU oracle runs in well under a
+    second each)."""
+    g = rng(seed)
+    out = []
+    for i in range(n):
+        out.append(Workload(f"small{seed}_{i}", nx=nx, ny=int(ny_choices[g.integers(0, len(ny_choices))]),
+                            phiy_min=-phi, phiy_max=phi, E_dc=float(g.uniform(0.0, 4.0)),
+                            E_w=0.1, omega=float(g.uniform(1.5, 4.0)), B=float(g.uniform(0.0, 3.0)),
+                            mu=float(g.choice([1.0, 2.0])), dt=dt))
+    return out

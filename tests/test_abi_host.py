@@ -78,3 +78,35 @@ def test_flags_must_be_zero():
     p.flags = 1
     with pytest.raises(bte.BteError):
         bte.bte_workspace_bytes(_grid(), p)
+
+
+def _cfg(**kw):
+    d = dict(n_x=16, phiy_min=-6.0, phiy_max=6.0, dt=2e-3)
+    d.update(kw)
+    return bte.make_batch_config(**d)
+
+
+class _W:
+    def __init__(self, **kw):
+        self.__dict__.update(dict(E_dc=1.0, E_w=0.1, omega=2.0, B=1.0, mu=1.0, ny=41))
+        self.__dict__.update(kw)
+
+
+def test_batch_workspace_bytes_and_validation():
+    n1 = bte.bte_batch_workspace_bytes(_cfg(), [_W(), _W(ny=41)])
+    n2 = bte.bte_batch_workspace_bytes(_cfg(), [_W(), _W(ny=401)])
+    assert n2 > n1 > 0
+    for cfg, inst, needle in [
+        (_cfg(min_periods=1), [_W()], "min_periods"),
+        (_cfg(tol=0.0), [_W()], "tol"),
+        (_cfg(), [_W(omega=0.0)], "omega"),
+        (_cfg(), [_W(ny=2)], "n_y"),
+        (_cfg(), [_W(B=1e4)], "leap-frog"),
+        (_cfg(precision=3), [_W()], "precision"),
+    ]:
+        with pytest.raises(bte.BteError) as ei:
+            bte.bte_batch_workspace_bytes(cfg, inst)
+        assert ei.value.status == bte.BTE_EINVAL and needle in str(ei.value)
+    bad = bte.bte_batch_tuning(bte.BTE_KERNEL_TWO_PASS, 8, 8, 0)   # not a batch kernel form
+    with pytest.raises(bte.BteError):
+        bte.bte_batch_workspace_bytes(_cfg(), [_W()], bad)
