@@ -237,13 +237,18 @@ bte_status bte_batch_create(const bte_batch_config* cfg, int32_t n, const bte_in
 
 /* Warm start: a device array of n x 64 x 128 floats (instance-major).  For
    instance i, rows 0..31 hold a_n - a^(0)_n (n = 0..31) and rows 32..63 hold
-   b_n (n = 1..32), each sampled at 128 uniform points of the phi_y box and
-   divided by the envelope exp(-mu phi_y^2 / 2).  Instances start from the
-   linearly interpolated, re-enveloped state (harmonics >= 32 from the
-   equilibrium) instead of f0, at t = 0; the start-up half-step then derives
-   the fractional grid.  NULL restores the equilibrium start.  The array must
-   stay valid until the next bte_batch_run completes. */
+   b_n (n = 1..32), each sampled at 128 uniform points phi_min + j (phi_max -
+   phi_min)/127 of the box.  Instances start from the state linearly
+   interpolated back to their phi_y grid (harmonics >= 32 from the
+   equilibrium) instead of f0, at t = 0 (phase 0 of the field); the start-up
+   half-step then derives the fractional grid.  NULL restores the equilibrium
+   start.  The array must stay valid until the next bte_batch_run completes. */
 bte_status bte_batch_set_warm_start(bte_batch* b, const float* dev_coeffs);
+
+/* State output: a device array of n x 64 x 128 floats that each run fills
+   with every instance's whole-grid state at the end of its last period
+   (phase 0 of the field), in the warm-start encoding above.  NULL: none. */
+bte_status bte_batch_set_state_output(bte_batch* b, float* dev_coeffs);
 
 /* Queue the sweep (one graph launch); returns immediately. */
 bte_status bte_batch_run(bte_batch* b);

@@ -109,6 +109,7 @@ def _load():
         "bte_batch_create": ([P(bte_batch_config), ctypes.c_int32, P(bte_instance),
                               P(bte_batch_tuning), vp, ctypes.c_size_t, vp, P(vp)], ctypes.c_int),
         "bte_batch_set_warm_start": ([vp, vp], ctypes.c_int),
+        "bte_batch_set_state_output": ([vp, vp], ctypes.c_int),
         "bte_batch_run": ([vp], ctypes.c_int),
         "bte_batch_results": ([vp, P(bte_result)], ctypes.c_int),
         "bte_batch_get_tuning": ([vp, P(bte_batch_tuning)], ctypes.c_int),
@@ -244,6 +245,11 @@ def bte_batch_set_warm_start(h: int, dev_ptr: int):
            "bte_batch_set_warm_start")
 
 
+def bte_batch_set_state_output(h: int, dev_ptr: int):
+    _check(_lib.bte_batch_set_state_output(ctypes.c_void_p(h), ctypes.c_void_p(dev_ptr or None)),
+           "bte_batch_set_state_output")
+
+
 def bte_batch_run(h: int):
     _check(_lib.bte_batch_run(ctypes.c_void_p(h)), "bte_batch_run")
 
@@ -344,6 +350,37 @@ class Solver:
     def tuning(self) -> bte_tuning:
         return bte_get_tuning(self.handle)
 
+    def run_periods(self, tol=1e-6, min_periods=2, max_periods=400):
+        """Advance whole ac periods from a fresh solver (step 0 = phase 0) until
+        the period-averaged absorption changes by less than `tol` between
+        consecutive periods: the batched sweep's criterion, period p covering
+        steps (rint((p-1) T/dt), rint(p T/dt)].  Returns a dict shaped like the
+        entries of Batch.results()."""
+        import math
+        per = 2.0 * math.pi / (self.params.omega * self.params.dt)
+        k, p, prev = 0, 0, None
+        out = dict(absorption=0.0, v_avg=0.0, dA=0.0, steps=0, periods=0, converged=0,
+                   status=BTE_OK)
+        while True:
+            p += 1
+            end = int(round(p * per))
+            self.set_window(k, end)
+            self.step(end - k)
+            k = end
+            o = self.observables()
+            dA = abs(o.absorption - prev) if prev is not None else 0.0
+            out.update(absorption=o.absorption, v_avg=o.v_avg, dA=dA, steps=k, periods=p,
+                       status=int(o.status))
+            if o.status != BTE_OK or not math.isfinite(o.absorption):
+                break
+            if p >= min_periods and p > 1 and dA < tol:
+                out["converged"] = 1
+                break
+            if p >= max_periods:
+                break
+            prev = o.absorption
+        return out
+
     def set_tuning(self, kernel=None, rows_per_wave=None, waves_per_block=None, graph_steps=None):
         t = self.tuning()
         if kernel is not None:
@@ -427,6 +464,18 @@ class Batch:
         assert tuple(coeffs.shape) == (self.n, 64, 128)
         self._warm = coeffs
         bte_batch_set_warm_start(self.handle, coeffs.data_ptr())
+
+    def set_state_output(self, out):
+        """out: a contiguous float32 CUDA tensor of shape (n, 64, 128) that each
+        run fills with the converged states (warm-start encoding), or None."""
+        if out is None:
+            self._out = None
+            bte_batch_set_state_output(self.handle, 0)
+            return
+        assert out.is_cuda and out.dtype.is_floating_point and out.is_contiguous()
+        assert tuple(out.shape) == (self.n, 64, 128)
+        self._out = out
+        bte_batch_set_state_output(self.handle, out.data_ptr())
 
     def run(self, wait=True, report_every=20.0, log=print):
         """Queue the sweep; with wait=True block until it finishes, printing the

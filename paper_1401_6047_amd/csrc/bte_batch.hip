@@ -50,6 +50,7 @@ struct BatchArgs {
     const double* s_all;      // [n][nx] source coefficients
     const int32_t* order;     // work order (instance indices)
     const float* warm;        // [n][64][128] or null
+    float* state_out;         // [n][64][128] or null: encoded final state
     bte_result* results;
     int32_t* queue;           // next-instance counter
     char* slots;              // per-workgroup state slots
@@ -173,10 +174,10 @@ __global__ __launch_bounds__(kMaxWavesPerGroup * kWave) void k_batch(BatchArgs<T
                     const int j0 = min(static_cast<int>(u), kWarmCols - 2);
                     const double w = u - j0;
                     const float* ra = warm + n * kWarmCols;
-                    a += g * ((1.0 - w) * ra[j0] + w * ra[j0 + 1]);
+                    a += (1.0 - w) * ra[j0] + w * ra[j0 + 1];
                     if (n >= 1) {
                         const float* rb = warm + (kWarmHarmonics + n - 1) * kWarmCols;
-                        b = g * ((1.0 - w) * rb[j0] + w * rb[j0 + 1]);
+                        b = (1.0 - w) * rb[j0] + w * rb[j0 + 1];
                     }
                 }
             }
@@ -284,6 +285,33 @@ __global__ __launch_bounds__(kMaxWavesPerGroup * kWave) void k_batch(BatchArgs<T
             }
             if (p >= B.max_periods) break;
             A_prev = A_p;
+        }
+        if (B.state_out) {
+            // the converged whole-grid state (phase 0 of the last period) in the
+            // warm-start encoding: a_n - a^(0)_n and b_n at 128 uniform phi_y
+            // points, linear interpolation between grid points
+            float* out = B.state_out + static_cast<size_t>(idx) * kWarmRows * kWarmCols;
+            const T* pa = plane(cur, 0);
+            const T* pb = plane(cur, 1);
+            for (int e = threadIdx.x; e < kWarmRows * kWarmCols; e += blockDim.x) {
+                const int row = e / kWarmCols, j = e - row * kWarmCols;
+                const int n = row < kWarmHarmonics ? row : row - kWarmHarmonics + 1;
+                double v = 0.0;
+                if (n < nx) {
+                    const double u = static_cast<double>(j) * (I.ny - 1) / (kWarmCols - 1);
+                    const int m0 = min(static_cast<int>(u), I.ny - 2);
+                    const double w = u - m0;
+                    const size_t o = static_cast<size_t>(n + kPadRows) * ld + (m0 + kPadCols);
+                    if (row < kWarmHarmonics) {
+                        const double d0 = static_cast<double>(pa[o]) - s_n[n] * g_m[m0];
+                        const double d1 = static_cast<double>(pa[o + 1]) - s_n[n] * g_m[m0 + 1];
+                        v = (1.0 - w) * d0 + w * d1;
+                    } else {
+                        v = (1.0 - w) * static_cast<double>(pb[o]) + w * static_cast<double>(pb[o + 1]);
+                    }
+                }
+                out[e] = static_cast<float>(v);
+            }
         }
         if (threadIdx.x == 0) {
             bte_result r{};
@@ -423,8 +451,10 @@ struct bte_batch {
     bool owns = false;
     BatchLayout L;
     const float* warm = nullptr;
+    float* state_out = nullptr;
     hipGraphExec_t graph = nullptr;
     const float* graph_warm = nullptr;
+    float* graph_out = nullptr;
     bool ran = false;
 };
 
@@ -439,6 +469,7 @@ hipError_t capture_batch(bte_batch* b)
     A.s_all = reinterpret_cast<const double*>(ws + b->L.off_s);
     A.order = reinterpret_cast<const int32_t*>(ws + b->L.off_order);
     A.warm = b->warm;
+    A.state_out = b->state_out;
     A.results = reinterpret_cast<bte_result*>(ws + b->L.off_results);
     A.queue = reinterpret_cast<int32_t*>(ws + b->L.off_queue);
     A.slots = ws + b->L.off_slots;
@@ -490,6 +521,7 @@ bte_status build_batch_graph(bte_batch* b)
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) return bfail(BTE_EDEVICE, std::string("instantiate: ") + hipGetErrorString(e));
     b->graph_warm = b->warm;
+    b->graph_out = b->state_out;
     return BTE_OK;
 }
 
@@ -600,10 +632,17 @@ bte_status bte_batch_set_warm_start(bte_batch* b, const float* dev_coeffs)
     return BTE_OK;
 }
 
+bte_status bte_batch_set_state_output(bte_batch* b, float* dev_coeffs)
+{
+    if (!b) return bfail(BTE_EINVAL, "batch is NULL");
+    b->state_out = dev_coeffs;
+    return BTE_OK;
+}
+
 bte_status bte_batch_run(bte_batch* b)
 {
     if (!b) return bfail(BTE_EINVAL, "batch is NULL");
-    if (!b->graph || b->graph_warm != b->warm) {
+    if (!b->graph || b->graph_warm != b->warm || b->graph_out != b->state_out) {
         bte_status st = build_batch_graph(b);
         if (st != BTE_OK) return st;
     }

@@ -128,25 +128,32 @@ def test_zero_warm_start_is_cold_start_and_good_warm_start_saves_periods(bte, sm
     zero = b.results()
     b.close()
     assert zero == cold
-    # warm start from the converged state of a cold run (phase 0 of a period),
-    # encoded as the warm-start coefficients: it must converge in fewer periods
-    coeffs = np.zeros((len(small), 64, 128), dtype=np.float32)
-    for i, w in enumerate(small):
-        s = bte.Solver.from_workload(w)
-        per = 2.0 * math.pi / (w.omega * w.dt)
-        s.step(int(np.rint(cold[i]["periods"] * per)))
-        a, bb, _, _ = s.state()
-        s.close()
-        y = np.linspace(w.phiy_min, w.phiy_max, w.ny)
-        env = np.exp(-0.5 * w.mu * y ** 2)
-        a0 = oracle.equilibrium(oracle.Problem(nx=w.nx, ny=w.ny, phiy_min=w.phiy_min,
-                                               phiy_max=w.phiy_max, E_dc=0, E_w=0, omega=0,
-                                               B=0, mu=w.mu, dt=w.dt))
-        ys = np.linspace(w.phiy_min, w.phiy_max, 128)
-        for n in range(min(32, w.nx)):
-            coeffs[i, n] = np.interp(ys, y, (a[n] - a0[n]) / env)
-        for n in range(1, min(33, w.nx)):
-            coeffs[i, 32 + n - 1] = np.interp(ys, y, bb[n] / env)
+    # warm start from the converged states of a cold run (phase 0 of the last
+    # period), as exported by the sweep itself in the warm-start encoding
+    b = make_batch(bte, small)
+    out = torch.zeros((len(small), 64, 128), dtype=torch.float32, device="cuda")
+    b.set_state_output(out)
+    b.run(log=None)
+    again = b.results()
+    b.close()
+    assert again == cold
+    coeffs = out.cpu().numpy()
+    # the export is the final state: check one instance against a solver run
+    w, i = small[5], 5
+    s = bte.Solver.from_workload(w)
+    per = 2.0 * math.pi / (w.omega * w.dt)
+    s.step(int(np.rint(cold[i]["periods"] * per)))
+    a, bb, _, _ = s.state()
+    s.close()
+    y = np.linspace(w.phiy_min, w.phiy_max, w.ny)
+    ys = np.linspace(w.phiy_min, w.phiy_max, 128)
+    a0 = oracle.equilibrium(oracle.Problem(nx=w.nx, ny=w.ny, phiy_min=w.phiy_min,
+                                           phiy_max=w.phiy_max, E_dc=0, E_w=0, omega=0, B=0,
+                                           mu=w.mu, dt=w.dt))
+    for n in range(min(32, w.nx)):
+        np.testing.assert_allclose(coeffs[i, n], np.interp(ys, y, a[n] - a0[n]), atol=1e-6)
+    for n in range(1, min(33, w.nx)):
+        np.testing.assert_allclose(coeffs[i, 32 + n - 1], np.interp(ys, y, bb[n]), atol=1e-6)
     b = make_batch(bte, small)
     b.set_warm_start(torch.from_numpy(coeffs).cuda())
     b.run(log=None)
