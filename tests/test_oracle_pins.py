@@ -486,3 +486,70 @@ def test_window_sums_and_resume():
     np.testing.assert_array_equal(r2.a_h, r.a_h)
     np.testing.assert_array_equal(r2.b_f, r.b_f)
     np.testing.assert_array_equal(r2.v_trace, r.v_trace[250:])
+
+
+# ---------------------------------------------------------------------------
+# Crossed fields with an ac component: contractivity and linear response
+# ---------------------------------------------------------------------------
+def test_two_solutions_approach_each_other_as_exp_minus_t():
+    """The transport part of the Fourier system (Sec. 2) is skew in the norm
+    that weighs a_0 twice (chi(1) = 2 is what pairs a_0 with b_1), so the
+    difference of two solutions decays exactly as e^{-t}; the scheme keeps
+    this up to O(dt^2).  Seeded states, crossed fields with an ac component."""
+    s1 = W.smooth_state(1, 32, 121, phi=6.0)
+    s2 = W.smooth_state(2, 32, 121, phi=6.0)
+    w = np.ones((32, 1))
+    w[0] = 2.0
+    d0 = math.sqrt(np.sum(w * ((s1[0] - s2[0]) ** 2 + (s1[1] - s2[1]) ** 2)))
+    dev = []
+    for dt in (1e-3, 5e-4):
+        pb = oracle.Problem(nx=32, ny=121, phiy_min=-6.0, phiy_max=6.0, E_dc=6.0, E_w=0.1,
+                            omega=2.0, B=4.0, mu=1.0, dt=dt)
+        n = int(round(4.0 / dt))
+        r1 = oracle.run(pb, n, state=s1)
+        r2 = oracle.run(pb, n, state=s2)
+        for x1, y1, x2, y2, t in ((r1.a_h, r1.b_h, r2.a_h, r2.b_h, n * dt),
+                                  (r1.a_f, r1.b_f, r2.a_f, r2.b_f, (n + 0.5) * dt)):
+            d = math.sqrt(np.sum(w * ((x1 - x2) ** 2 + (y1 - y2) ** 2)))
+            dev.append(d / (d0 * math.exp(-t)) - 1.0)
+    assert max(abs(x) for x in dev) < 1e-4, dev
+    # second order in dt: halving dt divides the deviation by ~4
+    assert 3.5 < dev[0] / dev[2] < 4.5, dev
+
+
+def test_small_signal_absorption_matches_linear_response():
+    """At E_w -> 0 with B != 0 the absorption is the linear response of the
+    semi-discrete system around its dc steady state z_dc:
+    dz = (i omega - L(E_dc))^{-1} K z_dc with K z = (-n b_n, n a_n) (the E
+    terms), v(t) = v_dc + E_w Re[dv e^{i omega t}].  Averaged over the same
+    discrete window as the oracle, A agrees to O(E_w^2) + O(dt^2)."""
+    import scipy.sparse as sps
+    import scipy.sparse.linalg as spla
+    E_dc, B, mu, omega, E_w, dt = 6.0, 4.0, 3.0, 2.0, 1e-3, 1e-3
+    pb = oracle.Problem(nx=64, ny=201, phiy_min=-8.0, phiy_max=8.0, E_dc=E_dc, E_w=E_w,
+                        omega=omega, B=B, mu=mu, dt=dt)
+    n_end, (lo, hi) = W.periods_window(omega, dt, 12, 4)
+    r = oracle.run(pb, n_end, window=(lo, hi))
+    N, M = pb.nx, pb.ny
+    L = semidiscrete_operator(pb, E_dc).tocsc()
+    rhs = -np.concatenate([equilibrium_ref(pb).ravel(), np.zeros((N - 1) * M)])
+    z = spla.spsolve(L, rhs)
+    a = z[:N * M].reshape(N, M)
+    b = np.zeros_like(a)
+    b[1:] = z[N * M:].reshape(N - 1, M)
+    n = np.arange(N)[:, None]
+    Kz = np.concatenate([(-n * b).ravel(), (n * a)[1:].ravel()]).astype(complex)
+    eye = sps.identity(L.shape[0], format="csc")
+    dz = spla.spsolve((1j * omega * eye - L).tocsc(), Kz)
+    dphi = (pb.phiy_max - pb.phiy_min) / (M - 1)
+    v_dc = math.pi * dphi * b[1].sum()
+    dv = math.pi * dphi * dz[N * M:N * M + M].sum()
+    ratio = sp.ive(1, mu) / sp.ive(0, mu)
+    tk = np.arange(lo + 1, hi + 1) * dt
+    v_lin = v_dc + E_w * np.real(dv * np.exp(1j * omega * tk))
+    A_pred = (2.0 / ratio) * np.mean(v_lin * np.cos(omega * tk))
+    assert abs(r.absorption - A_pred) <= 5e-5 * abs(A_pred), (r.absorption, A_pred)
+    assert abs(r.v_avg - v_dc) <= 1e-6 * abs(v_dc)
+    # the ac part is a large share of A here, so the check sees the response
+    A_ac = (2.0 / ratio) * np.mean(E_w * np.real(dv * np.exp(1j * omega * tk)) * np.cos(omega * tk))
+    assert abs(A_ac) > 0.5 * abs(A_pred)
