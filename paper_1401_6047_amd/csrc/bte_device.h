@@ -385,14 +385,21 @@ __device__ __forceinline__ void fused_tile(const TileEnv<T>& A, int tile)
         }
     };
 
-    // R + 2 iterations, padded to a multiple of 3 so that the loop body is
-    // exactly periodic in the slot rotation (no register copies of loads in
-    // flight at the back edge); padding iterations store nothing.
-    const int jend = jlo + (r1 - jlo + 1 + 2) / 3 * 3;
-    for (int j = jlo; j < jend; j += 3) {
+    // R + 2 iterations, padded to a multiple of 6; padding iterations store
+    // nothing.  A loaded fractional row stays live for five iterations, so a
+    // body of six (two turns of the slot rotation) lets the register
+    // assignment repeat without copies of loads in flight at the back edge.
+    // The start-up loads land before the loop so that the wait counts at the
+    // loop head are those of the steady state.
+    const int jend = jlo + (r1 - jlo + 1 + 5) / 6 * 6;
+    __builtin_amdgcn_s_waitcnt(0);
+    for (int j = jlo; j < jend; j += 6) {
         iter(j, S[0], S[1], S[2]);
         iter(j + 1, S[1], S[2], S[0]);
         iter(j + 2, S[2], S[0], S[1]);
+        iter(j + 3, S[0], S[1], S[2]);
+        iter(j + 4, S[1], S[2], S[0]);
+        iter(j + 5, S[2], S[0], S[1]);
     }
 }
 
@@ -630,14 +637,25 @@ __device__ __forceinline__ void fused2_tile(const TileEnv<T>& A, int tile, doubl
             }
         };
 
-        // W1 rows jlo .. jhi (R + 6 iterations), padded to a multiple of 3 so the
-        // loop body is periodic in the slot rotation; padding iterations store nothing.
-        const int iters = (jhi - jlo + 1 + 2) / 3 * 3;
-        for (int i = 0; i < iters; i += 3) {
+        // W1 rows jlo .. jhi (R + 6 iterations), padded to a multiple of 6;
+        // padding iterations store nothing.  A loaded row stays live for five
+        // iterations, so a body of six (two turns of the slot rotation) lets
+        // the register assignment repeat without copies of rows still in
+        // flight at the loop's back edge (a copy would wait for the load).
+        const int iters = (jhi - jlo + 1 + 5) / 6 * 6;
+        // Let the start-up loads land before the loop: otherwise the wait
+        // counts at the loop head are those of the entry path (few younger
+        // operations in flight) on every turn, and each turn drains the
+        // memory pipeline.
+        __builtin_amdgcn_s_waitcnt(0);
+        for (int i = 0; i < iters; i += 6) {
             const int j = jfirst + D * i;
             iter(j, S[0], S[1], S[2]);
             iter(j + D, S[1], S[2], S[0]);
             iter(j + 2 * D, S[2], S[0], S[1]);
+            iter(j + 3 * D, S[0], S[1], S[2]);
+            iter(j + 4 * D, S[1], S[2], S[0]);
+            iter(j + 5 * D, S[2], S[0], S[1]);
         }
     };
     using Up = std::integral_constant<int, 1>;
