@@ -11,7 +11,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libbte.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("bte_kernels.hip", "bte_solver.hip", "bte_tune.hip", "bte_batch.hip")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("bte_kernels.hip", "bte_solver.hip", "bte_tune.hip", "bte_batch.hip",
+                                                     "bte_mlp.hip")]
 ARCH = os.environ.get("BTE_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

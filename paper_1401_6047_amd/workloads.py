@@ -156,3 +156,41 @@ def small_sweep_draws(n: int, seed: int, nx: int = 16, ny_choices=(41, 61, 81),
                             E_w=0.1, omega=float(g.uniform(1.5, 4.0)), B=float(g.uniform(0.0, 3.0)),
                             mu=float(g.choice([1.0, 2.0])), dt=dt))
     return out
+
+
+# --------------------------------------------------------------------------
+# Warm-start network: seeded initial parameters (flat, in the layout
+# W1 [256][5], b1, W2 [256][256], b2, W3 [8192][256], b3).  Weights are drawn
+# N(0, 1/fan_in), biases start at zero.
+# --------------------------------------------------------------------------
+MLP_SHAPES = ((256, 5), (256,), (256, 256), (256,), (8192, 256), (8192,))
+
+
+def mlp_init(seed: int, weight_gain: float = 1.0) -> np.ndarray:
+    g = rng(seed)
+    parts = []
+    for shape in MLP_SHAPES:
+        if len(shape) == 2:
+            parts.append(g.normal(0.0, weight_gain / math.sqrt(shape[1]), size=shape).ravel())
+        else:
+            parts.append(np.zeros(shape[0]))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def warm_sweep_draws(n: int, seed: int, nx: int = 24, ny_by_mu=None, phi: float = 8.0,
+                     dt: float = 2e-3):
+    """Seeded instances with the sweep's parameter distribution (E_dc, B ~
+    U[0,8], omega ~ U[0.5,4], E_w = 0.1, mu in {0.25, 1, 4}) on reduced grids,
+    for training and testing the warm start quickly."""
+    ny_by_mu = ny_by_mu or {0.25: 81, 1.0: 121, 4.0: 161}
+    g = rng(seed)
+    mus = np.array(sorted(ny_by_mu))
+    out = []
+    for i in range(n):
+        E_dc = float(g.uniform(0.0, 8.0))
+        B = float(g.uniform(0.0, 8.0))
+        omega = float(g.uniform(0.5, 4.0))
+        mu = float(mus[g.integers(0, len(mus))])
+        out.append(Workload(f"warm{seed}_{i}", nx=nx, ny=int(ny_by_mu[mu]), phiy_min=-phi,
+                            phiy_max=phi, E_dc=E_dc, E_w=0.1, omega=omega, B=B, mu=mu, dt=dt))
+    return out

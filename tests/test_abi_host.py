@@ -110,3 +110,27 @@ def test_batch_workspace_bytes_and_validation():
     bad = bte.bte_batch_tuning(bte.BTE_KERNEL_TWO_PASS, 8, 8, 0)   # not a batch kernel form
     with pytest.raises(bte.BteError):
         bte.bte_batch_workspace_bytes(_cfg(), [_W()], bad)
+
+
+def test_mlp_library_exports_and_host_validation():
+    from paper_1401_6047_amd import mlp
+    names = bte.header_functions(mlp.HEADER_PATH)
+    assert "bte_mlp_train_step" in names and "bte_mlp_forward" in names
+    out = subprocess.run(["nm", "-D", "--defined-only", bte.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = {line.split()[-1] for line in out.splitlines() if " T " in line}
+    assert not [n for n in names if n not in exported]
+    assert mlp.bte_mlp_param_count() == 2172672
+    b16 = mlp.bte_mlp_workspace_bytes(512, mlp.BTE_MLP_BF16)
+    b32 = mlp.bte_mlp_workspace_bytes(512, mlp.BTE_MLP_FP32)
+    # FP32 master parameters, gradient and two moments at least
+    assert b32 > b16 > 4 * 4 * 2172672
+    assert mlp.bte_mlp_workspace_bytes(513, 0) > b16
+    assert mlp.bte_mlp_workspace_bytes(0, 0) == 0
+    assert mlp.bte_mlp_workspace_bytes(64, 7) == 0
+    with pytest.raises(bte.BteError, match="workspace"):
+        mlp.bte_mlp_create(64, 0, 0, 1 << 30, 0)
+    with pytest.raises(bte.BteError, match="max_batch"):
+        mlp.bte_mlp_create(0, 0, 256, 1 << 30, 0)
+    with pytest.raises(bte.BteError, match="handle"):
+        mlp.bte_mlp_forward(0, None, 4, None)
