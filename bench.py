@@ -63,6 +63,12 @@ def parse():
     ap.add_argument("--rows-per-wave", type=int, default=0,
                     help="fix the launch shape instead of autotuning (with --waves-per-block)")
     ap.add_argument("--waves-per-block", type=int, default=0)
+    ap.add_argument("--sweep", type=int, default=512,
+                    help="instances of the batched-sweep measurement (0: skip)")
+    ap.add_argument("--sweep-fp64", type=int, default=12,
+                    help="of those, how many the plain FP64 solver also runs")
+    ap.add_argument("--warm-train", type=int, default=2048,
+                    help="coarse-grid training states for the warm-started sweep (0: no warm run)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     return ap.parse_args()
@@ -118,6 +124,45 @@ def main_run_form(run):
     return run["tuning"]["kernel"]
 
 
+KERNEL_SOURCES = ("bte_device.h", "bte_internal.h", "bte_kernels.hip")
+
+
+def kernel_source_hash():
+    """sha256 over the sources of the single-instance step kernels."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(HERE, "paper_1401_6047_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def counter_traffic(kernel, precision, tuning):
+    """HBM bytes per launch from a committed counter summary
+    (profiles/*_counters.txt: rocprofv3 FETCH_SIZE and WRITE_SIZE per dispatch,
+    scaled by what the same counters read for a plain copy of known size),
+    or None when no summary matches this kernel, precision and launch shape
+    or the kernel sources changed since the counters were taken."""
+    import glob
+    want = kernel_source_hash()
+    for path in sorted(glob.glob(os.path.join(HERE, "profiles", "*_counters.txt"))):
+        kv = {}
+        with open(path) as f:
+            for line in f:
+                if ":" in line and not line.startswith("#"):
+                    k, v = line.split(":", 1)
+                    kv[k.strip()] = v.strip()
+        try:
+            if (kv.get("kernel") == kernel and kv.get("precision") == precision
+                    and int(kv.get("rows_per_wave", -1)) == tuning["rows_per_wave"]
+                    and int(kv.get("waves_per_block", -1)) == tuning["waves_per_block"]
+                    and kv.get("source_sha256") == want):
+                return float(kv["traffic_bytes_per_launch"])
+        except (KeyError, ValueError):
+            continue
+    return None
+
+
 def cpu_baseline(w, sample_steps):
     import oracle
     pb = oracle.Problem(nx=w.nx, ny=w.ny, phiy_min=w.phiy_min, phiy_max=w.phiy_max,
@@ -135,6 +180,78 @@ def cpu_baseline(w, sample_steps):
             "cores": threads, "kind": "oracle",
             "sample": f"{w.name}: {sample_steps} whole steps from f0 (incl. start-up), "
                       f"FP64, {secs:.1f} s, OpenMP threads={threads}"}
+
+
+def sweep_bench(bte, torch, n, n_fp64, n_train, log):
+    """Instances per hour of the parameter sweep: the plain FP64 solver (one
+    instance at a time, per-period host check) on the first n_fp64 draws, the
+    batched FP32-bulk sweep (one graph-captured persistent launch) on all n,
+    cold and warm-started from the trained network.  Every run stops on
+    |A_p - A_{p-1}| < 1e-6; the absorption of the batched runs is compared
+    with the FP64 solver's on the common draws."""
+    from paper_1401_6047_amd import workloads as W
+    from paper_1401_6047_amd import warmstart
+    draws = W.sweep_draws(n)
+    nx, phi, dt = draws[0].nx, draws[0].phiy_max, draws[0].dt
+    out = {"workload": f"sweep of {n} seeded draws: E_dc, B ~ U[0,8], omega ~ U[0.5,4], "
+                       f"E_w = 0.1, mu in {{0.25,1,4}} -> N_y 401/801/1601, N_x {nx}, "
+                       f"phi_y in [-{phi:g},{phi:g}], dt {dt:g}, tol 1e-6",
+           "unit": "instances/hour"}
+    # plain FP64 solver, one instance after another
+    t0 = time.perf_counter()
+    ref = []
+    for w in draws[:n_fp64]:
+        s = bte.Solver.from_workload(w)
+        s.autotune(target_ms=0.5)
+        ref.append(s.run_periods(tol=1e-6, max_periods=400))
+        s.close()
+    torch.cuda.synchronize()
+    t_fp64 = time.perf_counter() - t0
+    log(f"  fp64 solver: {n_fp64} instances in {t_fp64:.1f} s")
+    cold, t_cold = warmstart.sweep(draws, nx, phi, dt)
+    log(f"  batched fp32 cold: {n} instances in {t_cold:.1f} s")
+    dA = [abs(a["absorption"] - b["absorption"]) for a, b in zip(ref, cold[:n_fp64])]
+    out["fp64_solver"] = {"instances": n_fp64, "wall_s": t_fp64,
+                          "value": n_fp64 / t_fp64 * 3600,
+                          "periods_mean": sum(r["periods"] for r in ref) / n_fp64}
+    out["batched_fp32"] = {"instances": n, "wall_s": t_cold, "value": n / t_cold * 3600,
+                           "periods_mean": sum(r["periods"] for r in cold) / n,
+                           "converged": sum(r["converged"] for r in cold),
+                           "abs_dA_vs_fp64_max": max(dA)}
+    if n_train > 0:
+        train = warmstart.coarse_draws(n_train, W.SWEEP_SEED + 101)
+        t0 = time.perf_counter()
+        tres, states, _ = warmstart.sweep_states(train, train[0].nx, phi, train[0].dt)
+        keep = torch.as_tensor([i for i, r in enumerate(tres) if r["converged"] == 1],
+                               device="cuda")
+        from paper_1401_6047_amd import mlp as M
+        feats = M.features_of([train[i] for i in keep.tolist()])
+        net, hist, _ = warmstart.train_network(feats, states.index_select(0, keep).contiguous(),
+                                               epochs=40, seed=W.SWEEP_SEED + 102)
+        torch.cuda.synchronize()
+        t_prep = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        pred = net.predict(M.features_of(draws))
+        torch.cuda.synchronize()
+        t_inf = time.perf_counter() - t0
+        net.close()
+        warm, t_warm = warmstart.sweep(draws, nx, phi, dt, warm=pred)
+        log(f"  batched fp32 warm: {n} instances in {t_warm:.1f} s "
+            f"(+{t_inf * 1e3:.0f} ms inference; training data + training {t_prep:.1f} s)")
+        dAw = [abs(a["absorption"] - b["absorption"]) for a, b in zip(ref, warm[:n_fp64])]
+        out["batched_fp32_warm"] = {
+            "instances": n, "wall_s": t_warm + t_inf, "value": n / (t_warm + t_inf) * 3600,
+            "periods_mean": sum(r["periods"] for r in warm) / n,
+            "converged": sum(r["converged"] for r in warm),
+            "abs_dA_vs_fp64_max": max(dAw),
+            "abs_dA_vs_cold_max": max(abs(a["absorption"] - b["absorption"])
+                                      for a, b in zip(cold, warm)),
+            "network": {"train_states": len(keep), "train_grid": "N_x 48, N_y 101/201/401, dt 1e-3",
+                        "epochs": 40, "final_loss": hist[-1], "prep_s": t_prep}}
+    best = out.get("batched_fp32_warm", out["batched_fp32"])
+    out["value"] = best["value"]
+    out["vs_fp64_solver"] = best["value"] / out["fp64_solver"]["value"]
+    return out
 
 
 def main():
@@ -170,10 +287,15 @@ def main():
         c = W.CROSSED
         variants[f"{c.name}_fp64"] = time_solver(bte, torch, c, 0, -1, 20000, 2000, at)
         variants[f"{c.name}_fp32"] = time_solver(bte, torch, c, 1, -1, 20000, 2000, at)
+        # the paper's own timing run (Table 1: 1094 MLUPS in float on its GPU)
+        t1 = W.TABLE1
+        variants[f"{t1.name}_fp32"] = time_solver(bte, torch, t1, 1, -1, 10000, 1000, at)
+        variants[f"{t1.name}_fp64"] = time_solver(bte, torch, t1, 0, -1, 10000, 1000, at)
 
     ms = main_run["ms"]
     line = {
-        "metric": "grid-point updates/s (N_x*N_y*steps/s) + % HBM peak",
+        "metric": "grid-point updates/s (N_x*N_y*steps/s) + % HBM peak; "
+                  "sweep instances/hr at 1e-5 absorption err vs FP64",
         "value": main_run["cell_steps_per_s"],
         "unit": "grid-point updates/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -187,7 +309,8 @@ def main():
                    "tuning": main_run["tuning"]},
         "roofline": {"bound": "hbm", "achieved": main_run["achieved_GBs"], "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": main_run["achieved_GBs"] / HBM_PEAK_GBS,
-                     "traffic": None,
+                     "traffic": counter_traffic(main_run["kernel"], args.precision,
+                                                main_run["tuning"]),
                      "kernel": main_run["kernel"],
                      "steps_per_launch": main_run["steps_per_launch"],
                      "bytes_per_launch": main_run["bytes_per_launch"],
@@ -209,6 +332,10 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         line["copy_probe_mib"] = args.copy_mib
+    if args.sweep > 0:
+        line["sweep"] = sweep_bench(bte, torch, args.sweep, min(args.sweep_fp64, args.sweep),
+                                    args.warm_train,
+                                    lambda *a, **k: print(*a, file=sys.stderr, flush=True))
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_sample_steps)
     print(json.dumps(line), flush=True)

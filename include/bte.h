@@ -107,6 +107,12 @@ typedef struct {
     double S_vc;         /* sum of v_dr cos(w t) over the window */
     double v_avg;        /* S_v / n_avg (0 if n_avg = 0) */
     double absorption;   /* (2 I_0(mu)/I_1(mu)) S_vc / n_avg  (Sec. 2 absorption) */
+    double S_c;          /* sum of cos(w t) over the window's steps */
+    double absorption_cov; /* (2 I_0/I_1) (S_vc - v_avg S_c) / n_avg: the same
+                            average with the mean of v taken out, which removes
+                            the leak of the dc drift into a window that is not
+                            a whole number of periods (identical on exact
+                            periods, where S_c = 0) */
     int32_t status;      /* BTE_OK or BTE_EUNSTABLE */
     int32_t reserved;
 } bte_obs;
@@ -178,9 +184,12 @@ bte_status bte_tune(const bte_grid* grid, const bte_params* params, void* worksp
    Every instance starts from the equilibrium (or a warm start), runs whole
    ac periods of T = 2 pi / omega, and stops when the absorption of two
    consecutive periods differs by less than `tol` (after at least
-   `min_periods`), or after `max_periods`.  Period p covers the steps
-   round((p-1) T/dt) < k <= round(p T/dt); its absorption A_p and mean drift
-   velocity follow the Sec. 2 definitions over those steps.  One persistent,
+   `min_periods`), or after `max_periods`.  With L = round(T/dt) steps per
+   period, period p covers the steps (p-1) L < k <= p L (windows of one
+   length: a window of whole steps misses T by up to half a step, and equal
+   windows keep that error the same from period to period instead of
+   alternating); its absorption A_p and mean drift velocity follow the Sec. 2
+   definitions over those steps.  One persistent,
    graph-captured kernel launch runs the whole sweep: each workgroup takes the
    next instance from a device work queue (largest expected cost first) and
    advances it to convergence with the same per-cell arithmetic as the
@@ -211,7 +220,11 @@ typedef struct {
 } bte_batch_tuning;
 
 typedef struct {
-    double absorption;      /* A_p of the last period run */
+    double absorption;      /* A_p of the last period run: (2 I_0/I_1) times the
+                               mean over the period's steps of (v - <v>) cos(w t)
+                               (Sec. 2 absorption; the mean of v is taken out
+                               because a period of whole steps is not exactly
+                               2 pi / w long, as bte_obs.absorption_cov) */
     double v_avg;           /* mean drift velocity of that period */
     double dA;              /* |A_p - A_{p-1}| of that period (0 if p = 1) */
     int64_t steps;          /* whole steps taken */

@@ -48,7 +48,8 @@ class bte_obs(ctypes.Structure):
                 ("v_dr", ctypes.c_double), ("norm", ctypes.c_double),
                 ("n_avg", ctypes.c_int64), ("S_v", ctypes.c_double),
                 ("S_vc", ctypes.c_double), ("v_avg", ctypes.c_double),
-                ("absorption", ctypes.c_double), ("status", ctypes.c_int32),
+                ("absorption", ctypes.c_double), ("S_c", ctypes.c_double),
+                ("absorption_cov", ctypes.c_double), ("status", ctypes.c_int32),
                 ("reserved", ctypes.c_int32)]
 
 
@@ -89,6 +90,10 @@ def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"HIP library {LIB_PATH} is not built; run "
                           "`python -m paper_1401_6047_amd.build`")
+    # torch provides device memory and streams: its HIP runtime has to be in
+    # the process before the library binds to one, so that both share it
+    # (loaded the other way round, the library's runtime saw no device)
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     P = ctypes.POINTER
     vp, dp = ctypes.c_void_p, P(ctypes.c_double)
@@ -352,33 +357,33 @@ class Solver:
 
     def run_periods(self, tol=1e-6, min_periods=2, max_periods=400):
         """Advance whole ac periods from a fresh solver (step 0 = phase 0) until
-        the period-averaged absorption changes by less than `tol` between
-        consecutive periods: the batched sweep's criterion, period p covering
-        steps (rint((p-1) T/dt), rint(p T/dt)].  Returns a dict shaped like the
-        entries of Batch.results()."""
+        the per-period absorption (bte_obs.absorption_cov) changes by less than
+        `tol` between consecutive periods: the batched sweep's criterion, period
+        p covering steps ((p-1) L, p L] with L = round(T/dt).  Returns a dict
+        shaped like the entries of Batch.results()."""
         import math
-        per = 2.0 * math.pi / (self.params.omega * self.params.dt)
+        L = max(1, int(round(2.0 * math.pi / (self.params.omega * self.params.dt))))
         k, p, prev = 0, 0, None
         out = dict(absorption=0.0, v_avg=0.0, dA=0.0, steps=0, periods=0, converged=0,
                    status=BTE_OK)
         while True:
             p += 1
-            end = int(round(p * per))
+            end = p * L
             self.set_window(k, end)
             self.step(end - k)
             k = end
             o = self.observables()
-            dA = abs(o.absorption - prev) if prev is not None else 0.0
-            out.update(absorption=o.absorption, v_avg=o.v_avg, dA=dA, steps=k, periods=p,
+            dA = abs(o.absorption_cov - prev) if prev is not None else 0.0
+            out.update(absorption=o.absorption_cov, v_avg=o.v_avg, dA=dA, steps=k, periods=p,
                        status=int(o.status))
-            if o.status != BTE_OK or not math.isfinite(o.absorption):
+            if o.status != BTE_OK or not math.isfinite(o.absorption_cov):
                 break
             if p >= min_periods and p > 1 and dA < tol:
                 out["converged"] = 1
                 break
             if p >= max_periods:
                 break
-            prev = o.absorption
+            prev = o.absorption_cov
         return out
 
     def set_tuning(self, kernel=None, rows_per_wave=None, waves_per_block=None, graph_steps=None):

@@ -37,7 +37,7 @@ constexpr int kWarmHarmonics = 32;
 struct BatchInst {
     double E_dc, E_w, omega, B, mu;
     double dphi;          // phi_y spacing of this instance
-    double period_steps;  // T / dt
+    int64_t period_steps; // L = round(T / dt): steps per period window
     double two_over_ratio1;   // 2 I_0(mu) / I_1(mu)
     double v_norm;        // pi sqrt(alpha) dphi: v_dr = v_norm sum_m b_1(m)
     int32_t ny;
@@ -72,6 +72,13 @@ __global__ void k_batch_reset(int32_t* queue)
 
 // Values every lane agrees on, made provably uniform (scalar registers).
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t uni(int64_t v)
+{
+    const uint64_t u = static_cast<uint64_t>(v);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(u));
+    const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(u >> 32));
+    return static_cast<int64_t>((static_cast<uint64_t>(hi) << 32) | lo);
+}
 __device__ __forceinline__ double uni(double v)
 {
     const int lo = __builtin_amdgcn_readfirstlane(__double2loint(v));
@@ -79,28 +86,15 @@ __device__ __forceinline__ double uni(double v)
     return __hiloint2double(hi, lo);
 }
 
-// Deterministic workgroup sum of two values (fixed order).
-__device__ __forceinline__ void group_sum2(double& x, double& y, double* red, int nwaves)
+// Sums over the 64 lanes of one wavefront (fixed butterfly order).
+__device__ __forceinline__ void wave_sum3(double& x, double& y, double& z)
 {
-    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
 #pragma unroll
     for (int o = kWave / 2; o > 0; o >>= 1) {
-        x += __shfl_down(x, o);
-        y += __shfl_down(y, o);
+        x += __shfl_xor(x, o);
+        y += __shfl_xor(y, o);
+        z += __shfl_xor(z, o);
     }
-    if (lane == 0) {
-        red[2 * wave] = x;
-        red[2 * wave + 1] = y;
-    }
-    __syncthreads();
-    double sx = 0, sy = 0;
-    for (int w = 0; w < nwaves; ++w) {
-        sx += red[2 * w];
-        sy += red[2 * w + 1];
-    }
-    x = sx;
-    y = sy;
-    __syncthreads();
 }
 
 template <typename T>
@@ -240,7 +234,7 @@ __global__ __launch_bounds__(kMaxWavesPerGroup * kWave) void k_batch(BatchArgs<T
         while (true) {
             ++p;
             const int64_t pstart = k;
-            const int64_t pend = static_cast<int64_t>(rint(p * I.period_steps));
+            const int64_t pend = static_cast<int64_t>(p) * I.period_steps;
             for (int m = threadIdx.x; m < I.ny; m += blockDim.x) {
                 acc_v[m] = 0.0;
                 acc_vc[m] = 0.0;
@@ -264,16 +258,36 @@ __global__ __launch_bounds__(kMaxWavesPerGroup * kWave) void k_batch(BatchArgs<T
                 cur = 1 - cur;
                 __syncthreads();
             }
-            // period reduction over phi_y (fixed order)
-            double sv = 0.0, svc = 0.0;
-            for (int m = threadIdx.x; m < I.ny; m += blockDim.x) {
-                sv += acc_v[m];
-                svc += acc_vc[m];
+            // period reduction over phi_y, and the cosine at the period's steps
+            // (the times the step kernels use), by wavefront 0 in a fixed
+            // order whatever the group size
+            double sv = 0.0, svc = 0.0, sc = 0.0;
+            if (wave == 0) {
+                const int lane = threadIdx.x;
+                for (int m = lane; m < I.ny; m += kWave) {
+                    sv += acc_v[m];
+                    svc += acc_vc[m];
+                }
+                for (int64_t kk = pstart + 1 + lane; kk <= pend; kk += kWave)
+                    sc += cos(cs.omega * (static_cast<double>(2 * kk) * cs.half_dt));
+                wave_sum3(sv, svc, sc);
+                if (lane == 0) {
+                    s_red[0] = sv;
+                    s_red[1] = svc;
+                    s_red[2] = sc;
+                }
             }
-            group_sum2(sv, svc, s_red, nwaves);
+            __syncthreads();
+            sv = s_red[0];
+            svc = s_red[1];
+            sc = s_red[2];
+            __syncthreads();
             const double K = static_cast<double>(pend - pstart);
             v_p = I.v_norm * sv / K;
-            A_p = I.two_over_ratio1 * I.v_norm * svc / K;
+            // mean of v cos(w t) with the mean of v taken out: a period window
+            // of whole steps is not exactly one period, and the dc drift would
+            // otherwise leak into A_p by up to |v| dt / T
+            A_p = I.two_over_ratio1 * I.v_norm * (svc - (sv / K) * sc) / K;
             dA = (p > 1) ? fabs(A_p - A_prev) : 0.0;
             if (!isfinite(A_p) || !isfinite(v_p)) {
                 status = BTE_EUNSTABLE;
@@ -591,7 +605,7 @@ bte_status bte_batch_create(const bte_batch_config* cfg, int32_t n, const bte_in
         y.mu = x.mu;
         y.ny = x.n_y;
         y.dphi = (cfg->phiy_max - cfg->phiy_min) / (x.n_y - 1);
-        y.period_steps = 2.0 * kPi / (x.omega * cfg->dt);
+        y.period_steps = std::max<int64_t>(1, std::llround(2.0 * kPi / (x.omega * cfg->dt)));
         std::vector<double> r = bte::bessel_ratio_table(x.mu, cfg->n_x);
         y.two_over_ratio1 = 2.0 / r[1];
         y.v_norm = kPi * std::sqrt(cfg->alpha) * y.dphi;

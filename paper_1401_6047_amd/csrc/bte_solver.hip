@@ -582,8 +582,16 @@ bte_status bte_observables(bte_solver* s, bte_obs* out)
     out->S_v = f * r[2];
     out->S_vc = f * r[3];
     if (out->n_avg > 0) {
-        out->v_avg = out->S_v / static_cast<double>(out->n_avg);
-        out->absorption = (2.0 / s->ratio1) * out->S_vc / static_cast<double>(out->n_avg);
+        const double K = static_cast<double>(out->n_avg);
+        out->v_avg = out->S_v / K;
+        out->absorption = (2.0 / s->ratio1) * out->S_vc / K;
+        // cosine at the accumulated steps, at the kernels' times (2 (k) half_dt)
+        const int64_t lo = std::max(s->win_lo, s->acc_from);
+        double sc = 0.0;
+        for (int64_t k = lo + 1; k <= lo + out->n_avg; ++k)
+            sc += std::cos(s->params.omega * (static_cast<double>(2 * k) * s->cs.half_dt));
+        out->S_c = sc;
+        out->absorption_cov = (2.0 / s->ratio1) * (out->S_vc - out->v_avg * sc) / K;
     }
     const bool bad = !std::isfinite(out->norm) || !std::isfinite(out->v_dr) ||
                      !std::isfinite(out->S_v) || !std::isfinite(out->S_vc) ||

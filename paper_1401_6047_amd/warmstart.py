@@ -1,0 +1,152 @@
+"""Learned warm start for parameter sweeps, end to end.
+
+    python -m paper_1401_6047_amd.warmstart --train 32768 --test 4096 --out result.json
+
+1. Training states: a batched sweep over seeded draws of the sweep's
+   parameter distribution runs every instance to periodic convergence and
+   exports its state at field phase 0 in the 64 x 128 encoding
+   (``bte_batch_set_state_output``).  The training sweep may use a coarser
+   grid and time step than the evaluation sweep: the encoding samples the
+   same phi_y box either way, and a warm start only has to be close.
+2. The network (``include/bte_mlp.h``) is trained on (parameters -> state)
+   by the library's own forward/backward/Adam kernels.
+3. Held-out draws at the evaluation resolution run twice, from f0 (cold) and
+   from the network's prediction (warm); each run stops on its own
+   period-to-period absorption criterion.  Reported: periods and wall time of
+   both, and the absorption difference between them.
+
+Everything numeric runs in ``libbte.so``; this module only sequences calls.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import time
+
+import numpy as np
+
+from . import bte
+from . import mlp as M
+from . import workloads as W
+
+
+def sweep_states(instances, nx, phiy, dt, precision=bte.BTE_FP32_BULK, tol=1e-6,
+                 max_periods=400, log=None):
+    """Run a batched sweep to convergence; return (results, states (n,64,128)
+    CUDA tensor, wall seconds)."""
+    import torch
+    cfg = bte.make_batch_config(nx, -phiy, phiy, dt, precision=precision, tol=tol,
+                                min_periods=2, max_periods=max_periods)
+    b = bte.Batch(cfg, instances)
+    out = torch.zeros((len(instances), 64, 128), dtype=torch.float32, device="cuda")
+    b.set_state_output(out)
+    secs = b.run(log=log)
+    res = b.results()
+    b.close()
+    return res, out, secs
+
+
+def sweep(instances, nx, phiy, dt, warm=None, precision=bte.BTE_FP32_BULK, tol=1e-6,
+          max_periods=400, log=None):
+    """Run a batched sweep (cold, or warm from coefficients); (results, seconds)."""
+    cfg = bte.make_batch_config(nx, -phiy, phiy, dt, precision=precision, tol=tol,
+                                min_periods=2, max_periods=max_periods)
+    b = bte.Batch(cfg, instances)
+    b.set_warm_start(warm)
+    secs = b.run(log=log)
+    res = b.results()
+    b.close()
+    return res, secs
+
+
+def coarse_draws(n, seed, nx=48, ny_by_mu=None, phiy=10.0, dt=1e-3):
+    """Training draws: the sweep distribution on a 4x coarser phi_y grid and a
+    10x larger time step than the sweep itself."""
+    ny_by_mu = ny_by_mu or {0.25: 101, 1.0: 201, 4.0: 401}
+    return W.warm_sweep_draws(n, seed, nx=nx, ny_by_mu=ny_by_mu, phi=phiy, dt=dt)
+
+
+def train_network(features, states, epochs, batch=256, lr=2e-3, lr_final=2e-5, seed=0,
+                  precision=M.BTE_MLP_BF16, log=None):
+    net = M.Mlp(max_batch=max(batch, 256), precision=precision)
+    net.set_params(W.mlp_init(seed))
+    net.fit_normalization(features, states)
+    t0 = time.perf_counter()
+    hist = net.train(features, states, epochs=epochs, batch=batch, lr=lr, lr_final=lr_final,
+                     seed=seed + 1, log=log, log_every=max(1, epochs // 10))
+    return net, hist, time.perf_counter() - t0
+
+
+def run(n_train, n_test, epochs, seed=W.SWEEP_SEED, train_nx=48, eval_nx=128, log=print):
+    import torch
+    stamp = time.perf_counter()
+
+    def say(msg):
+        if log:
+            log(f"[{time.perf_counter() - stamp:7.1f} s] {msg}", flush=True)
+
+    train = coarse_draws(n_train, seed + 1, nx=train_nx)
+    say(f"training sweep: {n_train} instances, {train_nx} harmonics, coarse grid")
+    tres, states, tsecs = sweep_states(train, train_nx, 10.0, train[0].dt, log=log)
+    ok = np.array([r["converged"] == 1 for r in tres])
+    say(f"  done in {tsecs:.1f} s; converged {ok.sum()}/{len(ok)}")
+    keep = torch.as_tensor(np.nonzero(ok)[0], device="cuda")
+    feats = M.features_of([w for w, k in zip(train, ok) if k])
+    states = states.index_select(0, keep).contiguous()
+    net, hist, secs_train = train_network(feats, states, epochs, seed=seed + 2, log=log)
+    say(f"trained {epochs} epochs in {secs_train:.1f} s: loss {hist[0]:.3e} -> {hist[-1]:.3e}")
+
+    test = W.sweep_draws(n_test, seed=seed + 3, nx=eval_nx)
+    t0 = time.perf_counter()
+    pred = net.predict(M.features_of(test))
+    torch.cuda.synchronize()
+    infer = time.perf_counter() - t0
+    net.close()
+    say(f"evaluation sweep: {n_test} held-out instances, cold start")
+    cold, csecs = sweep(test, eval_nx, 10.0, test[0].dt, log=log)
+    say(f"  cold: {csecs:.1f} s")
+    warm, wsecs = sweep(test, eval_nx, 10.0, test[0].dt, warm=pred, log=log)
+    say(f"  warm: {wsecs:.1f} s (+ {infer * 1e3:.1f} ms inference)")
+    pc = np.array([r["periods"] for r in cold])
+    pw = np.array([r["periods"] for r in warm])
+    dA = np.array([abs(a["absorption"] - b["absorption"]) for a, b in zip(cold, warm)])
+    return {
+        "train": {"instances": n_train, "converged": int(ok.sum()), "nx": train_nx,
+                  "ny_by_mu": {"0.25": 101, "1": 201, "4": 401}, "dt": train[0].dt,
+                  "sweep_s": tsecs, "epochs": epochs, "train_s": secs_train,
+                  "loss_first_epoch": hist[0], "loss_last_epoch": hist[-1]},
+        "test": {"instances": n_test, "nx": eval_nx,
+                 "ny_by_mu": {str(k): v for k, v in W.SWEEP_NY_BY_MU.items()},
+                 "dt": test[0].dt, "precision": "fp32-bulk"},
+        "cold": {"periods_total": int(pc.sum()), "periods_mean": float(pc.mean()),
+                 "wall_s": csecs, "converged": int(sum(r["converged"] for r in cold)),
+                 "instances_per_hour": n_test / csecs * 3600},
+        "warm": {"periods_total": int(pw.sum()), "periods_mean": float(pw.mean()),
+                 "wall_s": wsecs, "inference_s": infer,
+                 "converged": int(sum(r["converged"] for r in warm)),
+                 "instances_per_hour": n_test / (wsecs + infer) * 3600},
+        "period_ratio": float(pw.sum() / pc.sum()),
+        "speedup": float(csecs / (wsecs + infer)),
+        "abs_dA_max": float(dA.max()), "abs_dA_mean": float(dA.mean()),
+        "fewer_periods": int((pw < pc).sum()), "more_periods": int((pw > pc).sum()),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--train", type=int, default=4096)
+    ap.add_argument("--test", type=int, default=512)
+    ap.add_argument("--epochs", type=int, default=60)
+    ap.add_argument("--out", default="")
+    a = ap.parse_args()
+    res = run(a.train, a.test, a.epochs)
+    line = json.dumps(res)
+    print(line, flush=True)
+    if a.out:
+        with open(a.out, "w") as f:
+            f.write(line + "\n")
+
+
+if __name__ == "__main__":
+    main()

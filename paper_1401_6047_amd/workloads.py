@@ -78,7 +78,15 @@ FIG2_SMALL = Workload("fig2_64x201", nx=64, ny=201, phiy_min=-8.0, phiy_max=8.0,
                       E_dc=6.0, E_w=0.0, omega=0.0, B=4.0, mu=3.0, dt=1e-3,
                       n_steps=1000, window=(0, 0))
 
-WORKLOADS = {w.name: w for w in (ESAKI_TSU, CROSSED, LARGE, FIG2_SMALL)}
+# The run the paper times in its Table 1 (Sec. 7): 120 harmonics x 4000 phi_y
+# points on [-6, 6], E_dc = 7, B = 4, E_w = 0.1, omega = 10, mu = 116,
+# alpha = 0.9496, dt = 1e-4, t = 10.
+TABLE1 = Workload("table1_120x4000", nx=120, ny=4000, phiy_min=-6.0, phiy_max=6.0,
+                  E_dc=7.0, E_w=0.1, omega=10.0, B=4.0, mu=116.0, dt=1e-4, alpha=0.9496,
+                  n_steps=100000, window=(0, 0),
+                  note="the paper's timing workload: 120 x 4000, 1e5 steps")
+
+WORKLOADS = {w.name: w for w in (ESAKI_TSU, CROSSED, LARGE, FIG2_SMALL, TABLE1)}
 
 
 # --------------------------------------------------------------------------
