@@ -63,9 +63,9 @@ def parse():
     ap.add_argument("--rows-per-wave", type=int, default=0,
                     help="fix the launch shape instead of autotuning (with --waves-per-block)")
     ap.add_argument("--waves-per-block", type=int, default=0)
-    ap.add_argument("--sweep", type=int, default=512,
+    ap.add_argument("--sweep", type=int, default=192,
                     help="instances of the batched-sweep measurement (0: skip)")
-    ap.add_argument("--sweep-fp64", type=int, default=12,
+    ap.add_argument("--sweep-fp64", type=int, default=8,
                     help="of those, how many the plain FP64 solver also runs")
     ap.add_argument("--warm-train", type=int, default=2048,
                     help="coarse-grid training states for the warm-started sweep (0: no warm run)")
@@ -208,7 +208,7 @@ def sweep_bench(bte, torch, n, n_fp64, n_train, log):
     torch.cuda.synchronize()
     t_fp64 = time.perf_counter() - t0
     log(f"  fp64 solver: {n_fp64} instances in {t_fp64:.1f} s")
-    cold, t_cold = warmstart.sweep(draws, nx, phi, dt)
+    cold, t_cold = warmstart.sweep(draws, nx, phi, dt, log=log)
     log(f"  batched fp32 cold: {n} instances in {t_cold:.1f} s")
     dA = [abs(a["absorption"] - b["absorption"]) for a, b in zip(ref, cold[:n_fp64])]
     out["fp64_solver"] = {"instances": n_fp64, "wall_s": t_fp64,
@@ -221,7 +221,7 @@ def sweep_bench(bte, torch, n, n_fp64, n_train, log):
     if n_train > 0:
         train = warmstart.coarse_draws(n_train, W.SWEEP_SEED + 101)
         t0 = time.perf_counter()
-        tres, states, _ = warmstart.sweep_states(train, train[0].nx, phi, train[0].dt)
+        tres, states, _ = warmstart.sweep_states(train, train[0].nx, phi, train[0].dt, log=log)
         keep = torch.as_tensor([i for i, r in enumerate(tres) if r["converged"] == 1],
                                device="cuda")
         from paper_1401_6047_amd import mlp as M
@@ -235,7 +235,7 @@ def sweep_bench(bte, torch, n, n_fp64, n_train, log):
         torch.cuda.synchronize()
         t_inf = time.perf_counter() - t0
         net.close()
-        warm, t_warm = warmstart.sweep(draws, nx, phi, dt, warm=pred)
+        warm, t_warm = warmstart.sweep(draws, nx, phi, dt, warm=pred, log=log)
         log(f"  batched fp32 warm: {n} instances in {t_warm:.1f} s "
             f"(+{t_inf * 1e3:.0f} ms inference; training data + training {t_prep:.1f} s)")
         dAw = [abs(a["absorption"] - b["absorption"]) for a, b in zip(ref, warm[:n_fp64])]
