@@ -34,8 +34,10 @@ __global__ __launch_bounds__(512) void k_fused_step(StepArgs<T> A)
     fused_tile<T>(E, tile);
 }
 
+// Three wavefronts per SIMD: the loop's registers fit in 168 VGPRs (the
+// allocation granule rounds 169 up to 176, which would leave room for two).
 template <typename T>
-__global__ __launch_bounds__(256) void k_fused_step2(StepArgs<T> A)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_fused_step2(StepArgs<T> A)
 {
     __shared__ double s_tab[4][kWave];
     const int tile = wave_tile();
