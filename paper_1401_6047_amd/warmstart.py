@@ -111,6 +111,11 @@ def run(n_train, n_test, epochs, seed=W.SWEEP_SEED, train_nx=48, eval_nx=128, lo
     pc = np.array([r["periods"] for r in cold])
     pw = np.array([r["periods"] for r in warm])
     dA = np.array([abs(a["absorption"] - b["absorption"]) for a, b in zip(cold, warm)])
+    cells = np.array([eval_nx * w.ny for w in test], dtype=np.float64)
+    work_c = float(np.sum(cells * np.array([r["steps"] for r in cold])))
+    work_w = float(np.sum(cells * np.array([r["steps"] for r in warm])))
+    worst = int(np.argmax(dA))
+    wt = test[worst]
     return {
         "train": {"instances": n_train, "converged": int(ok.sum()), "nx": train_nx,
                   "ny_by_mu": {"0.25": 101, "1": 201, "4": 401}, "dt": train[0].dt,
@@ -121,11 +126,15 @@ def run(n_train, n_test, epochs, seed=W.SWEEP_SEED, train_nx=48, eval_nx=128, lo
                  "dt": test[0].dt, "precision": "fp32-bulk"},
         "cold": {"periods_total": int(pc.sum()), "periods_mean": float(pc.mean()),
                  "wall_s": csecs, "converged": int(sum(r["converged"] for r in cold)),
-                 "instances_per_hour": n_test / csecs * 3600},
+                 "instances_per_hour": n_test / csecs * 3600,
+                 "cell_steps": work_c, "cell_steps_per_s": work_c / csecs},
         "warm": {"periods_total": int(pw.sum()), "periods_mean": float(pw.mean()),
                  "wall_s": wsecs, "inference_s": infer,
                  "converged": int(sum(r["converged"] for r in warm)),
-                 "instances_per_hour": n_test / (wsecs + infer) * 3600},
+                 "instances_per_hour": n_test / (wsecs + infer) * 3600,
+                 "cell_steps": work_w, "cell_steps_per_s": work_w / wsecs},
+        "largest_dA": {"E_dc": wt.E_dc, "B": wt.B, "omega": wt.omega, "mu": wt.mu,
+                       "cold": cold[worst], "warm": warm[worst]},
         "period_ratio": float(pw.sum() / pc.sum()),
         "speedup": float(csecs / (wsecs + infer)),
         "abs_dA_max": float(dA.max()), "abs_dA_mean": float(dA.mean()),
