@@ -226,7 +226,8 @@ __global__ __launch_bounds__(kMaxWavesPerGroup * kWave) void k_batch(BatchArgs<T
         const int R1 = min(B.R, kWave - 2), R2 = min(B.R, kWave - 6);
         const int n1 = (nx + R1 - 1) / R1, n2 = (nx + R2 - 1) / R2;
         const int tiles1 = n1 * ((I.ny + kFusedCols - 1) / kFusedCols);
-        const int tiles2 = n2 * ((I.ny + kFused2Cols - 1) / kFused2Cols);
+        E.cgroup = nwaves;
+        const int tiles2 = fused2_tile_count(I.ny, n2, nwaves);
         int64_t k = 0;
         int cur = 0, p = 0, converged = 0;
         int32_t status = BTE_OK;

@@ -225,7 +225,17 @@ struct TileEnv {
     uint32_t salt;            // stochastic-rounding seed offset (instance)
     int R;                    // harmonics per wave
     int nchunks;              // ceil(nx / R)
+    int cgroup;               // two-step tiles: phi_y strips per column group (see fused2_tile)
 };
+
+// Tiles of the two-step kernel for a grid of `ncol` phi_y strips, in column
+// groups of `cgroup` strips (the last group padded): the kernels launch or
+// loop over this many tile indices and fused2_tile skips the padding.
+__host__ __device__ inline int fused2_tile_count(int ny, int nchunks, int cgroup)
+{
+    const int ncol = (ny + kFused2Cols - 1) / kFused2Cols;
+    return nchunks * ((ncol + cgroup - 1) / cgroup) * cgroup;
+}
 
 template <typename T>
 struct HalfEnv {
@@ -444,8 +454,20 @@ __device__ __forceinline__ void fused2_tile(const TileEnv<T>& A, int tile, doubl
 {
     const Consts& cs = A.cs;
     const int lane = threadIdx.x & (kWave - 1);
-    const int ct = tile / A.nchunks;
-    const int r0 = (tile - ct * A.nchunks) * A.R;
+    // Tile order: groups of `cgroup` neighbouring phi_y strips (the waves of
+    // one block) of one harmonic chunk, then the next chunk of the same
+    // strips, then the next group.  The waves of a block march in step over
+    // neighbouring strips, so the halo columns they share are read once from
+    // L2; the chunks of a group follow each other closely, so the halo
+    // harmonics neighbouring chunks share are too.
+    const int ncol_tiles = (cs.ny + kFused2Cols - 1) / kFused2Cols;
+    const int cg = A.cgroup;
+    const int within = tile % cg;
+    const int rest = tile / cg;
+    const int chunk = rest % A.nchunks;
+    const int ct = (rest / A.nchunks) * cg + within;
+    if (ct >= ncol_tiles) return;                     // padding of the last group
+    const int r0 = chunk * A.R;
     const int r1 = min(r0 + A.R, cs.nx);
     const int m = ct * kFused2Cols - 4 + lane;
     const bool col_ok = (m >= 0) && (m < cs.ny);
@@ -494,7 +516,6 @@ __device__ __forceinline__ void fused2_tile(const TileEnv<T>& A, int tile, doubl
     // A tile is "interior" when every row its stages compute is a harmonic
     // >= 2 inside the grid and every lane a phi_y column inside the box: no
     // boundary masks, chi = 1 and no b_0 row.
-    const int ncol_tiles = (cs.ny + kFused2Cols - 1) / kFused2Cols;
     const bool interior = (jlo >= 2) && (jhi < cs.nx) && (ct > 0) && (ct < ncol_tiles - 1) &&
                           (ct * kFused2Cols - 4 >= 0) && (ct * kFused2Cols + kWave - 5 < cs.ny);
 
@@ -660,7 +681,7 @@ __device__ __forceinline__ void fused2_tile(const TileEnv<T>& A, int tile, doubl
     };
     using Up = std::integral_constant<int, 1>;
     using Down = std::integral_constant<int, -1>;
-    const bool up = ((r0 / A.R) & 1) == 0;
+    const bool up = (chunk & 1) == 0;
     if (interior) {
         if (up) run(std::false_type{}, Up{});
         else run(std::false_type{}, Down{});

@@ -191,8 +191,9 @@ hipError_t launch_fused_step2(const Consts& cs, const Shape& sh, Planes<T> src, 
     A.env = make_env(cs, sh, src, dst, s_n, g_m, acc_v, acc_vc, kWave - 6);
     A.ctl = ctl;
     A.j_off = j_off;
-    A.ntiles = A.env.nchunks * ((cs.ny + kFused2Cols - 1) / kFused2Cols);
     const int wpb = std::min(sh.waves_per_block, 4);
+    A.env.cgroup = wpb;
+    A.ntiles = fused2_tile_count(cs.ny, A.env.nchunks, wpb);
     const int blocks = round_up8((A.ntiles + wpb - 1) / wpb);
     hipLaunchKernelGGL(k_fused_step2<T>, dim3(blocks), dim3(wpb * kWave), 0, st, A);
     return hipGetLastError();

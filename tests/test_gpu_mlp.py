@@ -192,3 +192,21 @@ def test_trained_warm_start_saves_periods_over_cold_start(M):
         K = 2.0 * math.pi / (test[i].omega * test[i].dt)
         tol = 1e-5 + 2.0 * abs(cold[i]["absorption"]) / K
         assert abs(cold[i]["absorption"] - warm[i]["absorption"]) < tol
+
+
+def test_out_of_range_rows_enter_as_zero_gradient_rows(M):
+    """An index outside the data set is not read: it counts in n but adds
+    nothing, so loss and gradient are those of the valid rows times n_valid/n."""
+    x, c = _data(40, 100)
+    valid = W.rng(41).permutation(100)[:30].astype(np.int32)
+    idx = np.concatenate([valid, np.array([-1, 100, 12345], dtype=np.int32)])
+    net = M.Mlp(max_batch=64, precision=M.BTE_MLP_FP32)
+    net.set_params(W.mlp_init(42))
+    net.fit_normalization(x, c)
+    l_all, g_all = net.loss_grad(x, c, index=idx)
+    l_val, g_val = net.loss_grad(x, c, index=valid)
+    f = len(valid) / len(idx)
+    assert abs(l_all - f * l_val) <= 1e-6 * l_val
+    np.testing.assert_allclose(g_all.cpu().numpy(), f * g_val.cpu().numpy(), rtol=1e-4,
+                               atol=1e-6 * float(g_val.abs().max()))
+    net.close()
