@@ -34,9 +34,9 @@ HBM_PEAK_GBS = 8000.0
 # four state values of both grids once per launch (8 values; the two-step
 # kernel covers two steps with them); a single half-step reads its own two
 # values and the other grid's two and writes two (6 values).
-VALUES_PER_CELL = {0: 8, 1: 6, 2: 8}      # kernel form -> state values moved per launch
-KERNEL_NAMES = {0: "k_fused_step", 1: "k_half_step", 2: "k_fused_step2"}
-FORM_NAMES = {"fused": 0, "two_pass": 1, "fused2": 2, "auto": -1}
+VALUES_PER_CELL = {0: 8, 1: 6, 2: 8, 3: 8}   # kernel form -> state values moved per launch
+KERNEL_NAMES = {0: "k_fused_step", 1: "k_half_step", 2: "k_fused_step2", 3: "k_fused_step3"}
+FORM_NAMES = {"fused": 0, "two_pass": 1, "fused2": 2, "fused3": 3, "auto": -1}
 
 
 def launches_for(kernel, steps):
@@ -44,6 +44,8 @@ def launches_for(kernel, steps):
         return 2 * steps
     if kernel == 2:
         return steps // 2 + steps % 2
+    if kernel == 3:
+        return steps // 3 + (1 if steps % 3 else 0)
     return steps
 
 
@@ -109,7 +111,7 @@ def time_solver(bte, torch, w, precision, kernel, steps, warmup, autotune=True, 
         "us_per_step": ms * 1e3 / steps,
         "avg_launch_us": avg_launch_s * 1e6,
         "bytes_per_launch": bytes_per_launch,
-        "kernel": KERNEL_NAMES[form], "steps_per_launch": 2 if form == 2 else 1,
+        "kernel": KERNEL_NAMES[form], "steps_per_launch": {2: 2, 3: 3}.get(form, 1),
         "achieved_GBs": bytes_per_launch / avg_launch_s / 1e9,
         "status": int(obs.status), "v_dr": obs.v_dr, "norm": obs.norm,
         "autotune_best_us_per_step": tuned_us,
@@ -280,7 +282,7 @@ def main():
         other = 1 - precision
         variants[f"{w.name}_{'fp32' if other else 'fp64'}"] = time_solver(
             bte, torch, w, other, kernel, args.steps, args.warmup, at)
-        for name, form in (("fused", 0), ("two_pass", 1)):
+        for name, form in (("fused", 0), ("two_pass", 1), ("fused2", 2), ("fused3", 3)):
             if form != main_run_form(main_run):
                 variants[f"{w.name}_{args.precision}_{name}"] = time_solver(
                     bte, torch, w, precision, form, args.steps, args.warmup, at)

@@ -63,9 +63,13 @@ typedef enum {
                                 fused, ping-pong state buffers */
     BTE_KERNEL_TWO_PASS = 1, /* two launches per step, each half-step in place
                                 (the paper's two-kernel structure) */
-    BTE_KERNEL_FUSED2 = 2    /* one launch per two steps: four half-steps chained
+    BTE_KERNEL_FUSED2 = 2,   /* one launch per two steps: four half-steps chained
                                 in registers, ping-pong state buffers (an odd
                                 step count ends with one BTE_KERNEL_FUSED step) */
+    BTE_KERNEL_FUSED3 = 3    /* one launch per three steps: six half-steps
+                                chained in registers, ping-pong state buffers
+                                (a remainder of two or one steps runs as one
+                                FUSED2 or FUSED launch) */
 } bte_kernel;
 
 typedef struct {
@@ -92,8 +96,9 @@ typedef struct {
    for the grid; bte_tune() picks one by measurement. */
 typedef struct {
     int32_t kernel;          /* bte_kernel */
-    int32_t rows_per_wave;   /* harmonics handled by one wavefront, 1 .. 62 (58 for FUSED2) */
-    int32_t waves_per_block; /* 1, 2, 4 or 8 */
+    int32_t rows_per_wave;   /* harmonics handled by one wavefront, 1 .. 62 (used up to 58
+                                for FUSED2 and 54 for FUSED3) */
+    int32_t waves_per_block; /* 1, 2, 4 or 8 (used up to 4 for FUSED2 and FUSED3) */
     int32_t graph_steps;     /* steps per captured HIP graph (even), 0 = no graph */
 } bte_tuning;
 

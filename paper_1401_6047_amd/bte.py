@@ -20,7 +20,7 @@ HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "bte.h")
 
 BTE_OK, BTE_EINVAL, BTE_ENOMEM, BTE_EDEVICE, BTE_EUNSTABLE, BTE_ESTATE = 0, -1, -2, -3, -4, -5
 BTE_FP64, BTE_FP32_BULK = 0, 1
-BTE_KERNEL_FUSED, BTE_KERNEL_TWO_PASS, BTE_KERNEL_FUSED2 = 0, 1, 2
+BTE_KERNEL_FUSED, BTE_KERNEL_TWO_PASS, BTE_KERNEL_FUSED2, BTE_KERNEL_FUSED3 = 0, 1, 2, 3
 STATUS_NAMES = {0: "BTE_OK", -1: "BTE_EINVAL", -2: "BTE_ENOMEM", -3: "BTE_EDEVICE",
                 -4: "BTE_EUNSTABLE", -5: "BTE_ESTATE"}
 

@@ -221,7 +221,7 @@ struct TileEnv {
     double* acc_vc;
     Consts cs;
     int64_t k;                // step of the source state
-    bool acc1, acc2;          // steps k+1, k+2 enter the window sums
+    bool acc1, acc2, acc3;    // steps k+1, k+2, k+3 enter the window sums
     uint32_t salt;            // stochastic-rounding seed offset (instance)
     int R;                    // harmonics per wave
     int nchunks;              // ceil(nx / R)
@@ -234,6 +234,12 @@ struct TileEnv {
 __host__ __device__ inline int fused2_tile_count(int ny, int nchunks, int cgroup)
 {
     const int ncol = (ny + kFused2Cols - 1) / kFused2Cols;
+    return nchunks * ((ncol + cgroup - 1) / cgroup) * cgroup;
+}
+
+__host__ __device__ inline int fused3_tile_count(int ny, int nchunks, int cgroup)
+{
+    const int ncol = (ny + kFused3Cols - 1) / kFused3Cols;
     return nchunks * ((ncol + cgroup - 1) / cgroup) * cgroup;
 }
 
@@ -668,6 +674,273 @@ __device__ __forceinline__ void fused2_tile(const TileEnv<T>& A, int tile, doubl
         // counts at the loop head are those of the entry path (few younger
         // operations in flight) on every turn, and each turn drains the
         // memory pipeline.
+        __builtin_amdgcn_s_waitcnt(0);
+        for (int i = 0; i < iters; i += 6) {
+            const int j = jfirst + D * i;
+            iter(j, S[0], S[1], S[2]);
+            iter(j + D, S[1], S[2], S[0]);
+            iter(j + 2 * D, S[2], S[0], S[1]);
+            iter(j + 3 * D, S[0], S[1], S[2]);
+            iter(j + 4 * D, S[1], S[2], S[0]);
+            iter(j + 5 * D, S[2], S[0], S[1]);
+        }
+    };
+    using Up = std::integral_constant<int, 1>;
+    using Down = std::integral_constant<int, -1>;
+    const bool up = (chunk & 1) == 0;
+    if (interior) {
+        if (up) run(std::false_type{}, Up{});
+        else run(std::false_type{}, Down{});
+    } else {
+        if (up) run(std::true_type{}, Up{});
+        else run(std::true_type{}, Down{});
+    }
+}
+
+// ---- three steps per pass ----------------------------------------------------
+// Registers of one slot (rows congruent mod 3) of the three-step pipeline.
+struct Row3Regs {
+    double f0a, f0b, f0da, f0db;   // old fractional grid z^{k+1/2}: own, phi_y differences
+    double h1a, h1b, h1da, h1db;   // whole grid z^{k+1}
+    double f1a, f1b, f1da, f1db;   // fractional grid z^{k+3/2}
+    double h2a, h2b, h2da, h2db;   // whole grid z^{k+2}
+    double f2a, f2b, f2da, f2db;   // fractional grid z^{k+5/2}
+    double h3da, h3db;             // whole grid z^{k+3}: differences
+    double nfa, nfb, nha, nhb;     // loads in flight (old fractional row j+D, old whole row j)
+};
+
+// Three leap-frog steps in one pass over the state: the two-step pipeline
+// extended by two more stages.  Iteration j of the march computes
+//   W1: z^{k+1} at j,  F1: z^{k+3/2} at j-D,  W2: z^{k+2} at j-2D,
+//   F2: z^{k+5/2} at j-3D,  W3: z^{k+3} at j-4D,  F3: z^{k+7/2} at j-5D
+// (D = +1 or -1, the march direction) and writes z^{k+3} and z^{k+7/2}: the
+// state is read and written once per three steps.  Each stage is valid one
+// lane further in, so a tile keeps six halo lanes on each side (52 output
+// lanes, 6..57) and five or six halo harmonics.  Per cell the arithmetic is
+// exactly that of the one-step kernel.
+template <typename T>
+__device__ __forceinline__ void fused3_tile(const TileEnv<T>& A, int tile, double* s_tab)
+{
+    const Consts& cs = A.cs;
+    const int lane = threadIdx.x & (kWave - 1);
+    // tile order as in fused2_tile: column groups of `cgroup` strips
+    const int ncol_tiles = (cs.ny + kFused3Cols - 1) / kFused3Cols;
+    const int cg = A.cgroup;
+    const int within = tile % cg;
+    const int rest = tile / cg;
+    const int chunk = rest % A.nchunks;
+    const int ct = (rest / A.nchunks) * cg + within;
+    if (ct >= ncol_tiles) return;                     // padding of the last group
+    const int r0 = chunk * A.R;
+    const int r1 = min(r0 + A.R, cs.nx);
+    const int m = ct * kFused3Cols - 6 + lane;
+    const bool col_ok = (m >= 0) && (m < cs.ny);
+    const bool out_lane = (lane >= 6) && (lane < kWave - 6) && col_ok;
+
+    const int64_t k = A.k;
+    // cos(omega t) at the half-step times 2k .. 2k+7, lane i holds time 2k+i
+    double cw[8];
+    {
+        const double t = static_cast<double>(2 * k + min(lane, 7)) * cs.half_dt;
+        const double v = cos(cs.omega * t);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) cw[i] = __shfl(v, i);
+    }
+    const bool acc1 = A.acc1, acc2 = A.acc2, acc3 = A.acc3;
+
+    const double phi = fma(static_cast<double>(m), cs.dphi, cs.phimin);
+    const double gdt = (col_ok ? A.g_m[m] : 0.0) * cs.dt;
+    const double hdt = 0.5 * cs.dt;
+    double q[8];                                      // (E(t_i) + B phi) dt/2
+#pragma unroll
+    for (int i = 0; i < 8; ++i) q[i] = (fma(cs.E_w, cw[i], cs.E_dc) + cs.B * phi) * hdt;
+    const double c = cs.c_full, nu = cs.nu, xi = cs.xi, nu2 = cs.nu * cs.nu;
+    // s_n of harmonics r0-5 .. r0+58, one per lane
+    const int sbase = r0 - 5;
+    s_tab[lane] = A.s_n[min(max(sbase + lane, 0), cs.nx - 1)];
+    __builtin_amdgcn_wave_barrier();
+    auto a0dt = [&](int n) { return s_tab[min(max(n - sbase, 0), kWave - 1)] * gdt; };
+
+    const uint32_t rb = static_cast<uint32_t>(cs.ld) * sizeof(T);
+    // the two leftmost halo lanes of the first column tile lie left of the
+    // zero border: they read its outermost (zero) column
+    const uint32_t cb = static_cast<uint32_t>(max(m, -kPadCols) + kPadCols) * sizeof(T);
+    const uint32_t pb = static_cast<uint32_t>(cs.nx + 2 * kPadRows) * rb;
+    const RowAddr<T> aHs(A.src.a_h, pb, rb, cb);
+    const RowAddr<T> bHs(A.src.b_h, pb, rb, cb);
+    const RowAddr<T> aFs(A.src.a_f, pb, rb, cb);
+    const RowAddr<T> bFs(A.src.b_f, pb, rb, cb);
+    const RowAddr<T> aHd(A.dst.a_h, pb, rb, cb, plane_seed(k, 0 + A.salt));
+    const RowAddr<T> bHd(A.dst.b_h, pb, rb, cb, plane_seed(k, 1 + A.salt));
+    const RowAddr<T> aFd(A.dst.a_f, pb, rb, cb, plane_seed(k, 2 + A.salt));
+    const RowAddr<T> bFd(A.dst.b_f, pb, rb, cb, plane_seed(k, 3 + A.salt));
+    // rows beyond the zero border read its outermost (zero) row
+    const int rmin = -kPadRows, rmax = cs.nx + kPadRows - 1;
+
+    const int jlo = r0 - 5;                           // first W1 row
+    const int jhi = r1 + 4;                           // last W1 row
+    // interior: every stage row a harmonic >= 2 inside the grid and every
+    // lane a phi_y column inside the box (no masks, chi = 1, no b_0 row)
+    const bool interior = (jlo >= 2) && (jhi < cs.nx) && (ct * kFused3Cols - 6 >= 0) &&
+                          (ct * kFused3Cols - 6 + kWave - 1 < cs.ny);
+
+    auto run = [&](auto edge_tag, auto dir_tag) {
+        constexpr bool EDGE = decltype(edge_tag)::value;
+        constexpr int D = decltype(dir_tag)::value;
+        auto valid = [&](int n) { return (n >= 0) && (n < cs.nx) && col_ok; };
+        auto coupling = [&](int n, double behind_a, double ahead_a, double behind_b,
+                            double ahead_b, double& At, double& Bt) {
+            const double lo_a = D > 0 ? behind_a : ahead_a, hi_a = D > 0 ? ahead_a : behind_a;
+            const double lo_b = D > 0 ? behind_b : ahead_b, hi_b = D > 0 ? ahead_b : behind_b;
+            if constexpr (EDGE)
+                At = c * ((n == 1 ? 2.0 * lo_a : lo_a) - hi_a);
+            else
+                At = c * (lo_a - hi_a);
+            Bt = c * (hi_b - lo_b);
+        };
+        auto mask = [&](int n, double& a, double& b) {
+            if constexpr (EDGE) {
+                const bool v = valid(n);
+                a = v ? a : 0.0;
+                b = (v && n >= 1) ? b : 0.0;
+            }
+        };
+        auto accumulate = [&](int n, double hb, double cwt, bool on) {
+            if constexpr (EDGE) {
+                if (n == 1 && n >= r0 && n < r1 && out_lane && on) {
+                    A.acc_v[m] += hb;
+                    A.acc_vc[m] += hb * cwt;
+                }
+            }
+        };
+
+        const int jfirst = D > 0 ? jlo : jhi;
+        Row3Regs S[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) S[i] = Row3Regs{};
+        auto issue = [&](Row3Regs& P, int j) {
+            const int jf = min(max(min(max(j + D, r0 - 6), r1 + 5), rmin), rmax);
+            const int jh = min(max(min(max(j, jlo), jhi), rmin), rmax);
+            P.nfa = aFs.load(jf);
+            P.nfb = bFs.load(jf);
+            P.nha = aHs.load(jh);
+            P.nhb = bHs.load(jh);
+        };
+        {
+            const int j0 = min(max(jfirst - D, rmin), rmax);
+            const int j1 = min(max(jfirst, rmin), rmax);
+            Row3Regs& a = S[0];                       // slot of jfirst - D
+            a.f0a = aFs.load(j0);
+            a.f0b = bFs.load(j0);
+            Row3Regs& b = S[1];                       // slot of jfirst
+            b.f0a = aFs.load(j1);
+            b.f0b = bFs.load(j1);
+            issue(S[1], jfirst);
+            issue(S[2], jfirst + D);
+            issue(S[0], jfirst + 2 * D);
+            a.f0da = dphi_diff(a.f0a);
+            a.f0db = dphi_diff(a.f0b);
+            b.f0da = dphi_diff(b.f0a);
+            b.f0db = dphi_diff(b.f0b);
+        }
+
+        // Pm: slot of row j - D, P0: row j, Pp: row j + D.  Rows j - 2D and
+        // j - 5D share Pp's slot, j - 3D shares P0's, j - 4D shares Pm's.
+        auto iter = [&](int j, Row3Regs& Pm, Row3Regs& P0, Row3Regs& Pp) {
+            Pp.f0a = P0.nfa;
+            Pp.f0b = P0.nfb;
+            const double ha0 = P0.nha, hb0 = P0.nhb;
+            issue(P0, j + 3 * D);
+            Pp.f0da = dphi_diff(Pp.f0a);
+            Pp.f0db = dphi_diff(Pp.f0b);
+            // W1: z^{k+1} at j (old fractional rows j -+ D in Pm, Pp)
+            {
+                const double nd = static_cast<double>(j);
+                double At, Bt, ha, hb;
+                coupling(j, Pm.f0da, Pp.f0da, Pm.f0db, Pp.f0db, At, Bt);
+                op_T2(ha0, hb0, At, Bt, a0dt(j), nd * q[0], nd * q[2], nu, nu2, xi, ha, hb);
+                mask(j, ha, hb);
+                P0.h1a = ha;
+                P0.h1b = hb;
+                P0.h1da = dphi_diff(ha);
+                P0.h1db = dphi_diff(hb);
+                accumulate(j, hb, cw[2], acc1);
+            }
+            // F1: z^{k+3/2} at j - D (z^{k+1} at j - 2D in Pp, j in P0)
+            {
+                const int n = j - D;
+                const double nd = static_cast<double>(n);
+                double At, Bt, fa, fb;
+                coupling(n, Pp.h1da, P0.h1da, Pp.h1db, P0.h1db, At, Bt);
+                op_T2(Pm.f0a, Pm.f0b, At, Bt, a0dt(n), nd * q[1], nd * q[3], nu, nu2, xi, fa, fb);
+                mask(n, fa, fb);
+                Pm.f1a = fa;
+                Pm.f1b = fb;
+                Pm.f1da = dphi_diff(fa);
+                Pm.f1db = dphi_diff(fb);
+            }
+            // W2: z^{k+2} at j - 2D (z^{k+3/2} at j - 3D in P0, j - D in Pm)
+            {
+                const int n = j - 2 * D;
+                const double nd = static_cast<double>(n);
+                double At, Bt, ha, hb;
+                coupling(n, P0.f1da, Pm.f1da, P0.f1db, Pm.f1db, At, Bt);
+                op_T2(Pp.h1a, Pp.h1b, At, Bt, a0dt(n), nd * q[2], nd * q[4], nu, nu2, xi, ha, hb);
+                mask(n, ha, hb);
+                Pp.h2a = ha;
+                Pp.h2b = hb;
+                Pp.h2da = dphi_diff(ha);
+                Pp.h2db = dphi_diff(hb);
+                accumulate(n, hb, cw[4], acc2);
+            }
+            // F2: z^{k+5/2} at j - 3D (z^{k+2} at j - 4D in Pm, j - 2D in Pp)
+            {
+                const int n = j - 3 * D;
+                const double nd = static_cast<double>(n);
+                double At, Bt, fa, fb;
+                coupling(n, Pm.h2da, Pp.h2da, Pm.h2db, Pp.h2db, At, Bt);
+                op_T2(P0.f1a, P0.f1b, At, Bt, a0dt(n), nd * q[3], nd * q[5], nu, nu2, xi, fa, fb);
+                mask(n, fa, fb);
+                P0.f2a = fa;
+                P0.f2b = fb;
+                P0.f2da = dphi_diff(fa);
+                P0.f2db = dphi_diff(fb);
+            }
+            // W3: z^{k+3} at j - 4D (z^{k+5/2} at j - 5D in Pp, j - 3D in P0)
+            {
+                const int n = j - 4 * D;
+                const double nd = static_cast<double>(n);
+                double At, Bt, ha, hb;
+                coupling(n, Pp.f2da, P0.f2da, Pp.f2db, P0.f2db, At, Bt);
+                op_T2(Pm.h2a, Pm.h2b, At, Bt, a0dt(n), nd * q[4], nd * q[6], nu, nu2, xi, ha, hb);
+                mask(n, ha, hb);
+                Pm.h3da = dphi_diff(ha);
+                Pm.h3db = dphi_diff(hb);
+                if (n >= r0 && n < r1 && out_lane) {
+                    aHd.store(n, ha);
+                    bHd.store(n, hb);
+                }
+                accumulate(n, hb, cw[6], acc3);
+            }
+            // F3: z^{k+7/2} at j - 5D (z^{k+3} at j - 6D in P0, j - 4D in Pm)
+            {
+                const int n = j - 5 * D;
+                if (n >= r0 && n < r1) {
+                    const double nd = static_cast<double>(n);
+                    double At, Bt, fa, fb;
+                    coupling(n, P0.h3da, Pm.h3da, P0.h3db, Pm.h3db, At, Bt);
+                    op_T2(Pp.f2a, Pp.f2b, At, Bt, a0dt(n), nd * q[5], nd * q[7], nu, nu2, xi, fa, fb);
+                    if (out_lane) {
+                        aFd.store(n, fa);
+                        bFd.store(n, (!EDGE || n >= 1) ? fb : 0.0);
+                    }
+                }
+            }
+        };
+
+        // W1 rows jlo .. jhi (R + 10 iterations), padded to a multiple of 6 (a
+        // loaded row lives five iterations; see fused2_tile)
+        const int iters = (jhi - jlo + 1 + 5) / 6 * 6;
         __builtin_amdgcn_s_waitcnt(0);
         for (int i = 0; i < iters; i += 6) {
             const int j = jfirst + D * i;

@@ -21,10 +21,11 @@ constexpr int kWave = 64;
 // Output columns of one wavefront.  A half-step needs the other grid one
 // column beyond its outputs, so a tile chaining h half-steps in registers
 // keeps h halo lanes on each side: the single half-step h = 1, the fused
-// step h = 2, the two-step kernel h = 4.
+// step h = 2, the two-step kernel h = 4, the three-step kernel h = 6.
 constexpr int kHalfCols = kWave - 2;
 constexpr int kFusedCols = kWave - 4;
 constexpr int kFused2Cols = kWave - 8;
+constexpr int kFused3Cols = kWave - 12;
 
 // Largest physical column (m + kPadCols) any tile of a kernel with `cols`
 // output columns and `halo` halo lanes touches for an N_y-column grid, + 1.
@@ -84,6 +85,13 @@ template <typename T>
 hipError_t launch_fused_step(const Consts& cs, const Shape& sh, Planes<T> src, Planes<T> dst,
                              const double* s_n, const double* g_m, double* acc_v,
                              double* acc_vc, const Ctl* ctl, int j_off, hipStream_t st);
+
+// Three fused leap-frog steps k -> k+3 in one pass (six half-steps chained in
+// registers), from `src` to `dst`.  The step index is ctl->k + j_off.
+template <typename T>
+hipError_t launch_fused_step3(const Consts& cs, const Shape& sh, Planes<T> src, Planes<T> dst,
+                              const double* s_n, const double* g_m, double* acc_v,
+                              double* acc_vc, const Ctl* ctl, int j_off, hipStream_t st);
 
 // Two fused leap-frog steps k -> k+2 in one pass (four half-steps chained in
 // registers), from `src` to `dst`.  The step index is ctl->k + j_off.

@@ -51,6 +51,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
 }
 
 template <typename T>
+__global__ __launch_bounds__(256) void k_fused_step3(StepArgs<T> A)
+{
+    __shared__ double s_tab[4][kWave];
+    const int tile = wave_tile();
+    if (tile >= A.ntiles) return;                    // wave-uniform
+    const Ctl ctl = *A.ctl;
+    TileEnv<T> E = A.env;
+    E.k = ctl.k + A.j_off;
+    E.acc1 = in_window(ctl, E.k + 1);
+    E.acc2 = in_window(ctl, E.k + 2);
+    E.acc3 = in_window(ctl, E.k + 3);
+    fused3_tile<T>(E, tile, &s_tab[threadIdx.x / kWave][0]);
+}
+
+template <typename T>
 struct HalfArgs {
     HalfEnv<T> env;
     int accumulate;
@@ -181,6 +196,25 @@ hipError_t launch_fused_step(const Consts& cs, const Shape& sh, Planes<T> src, P
 }
 
 template <typename T>
+hipError_t launch_fused_step3(const Consts& cs, const Shape& sh, Planes<T> src, Planes<T> dst,
+                              const double* s_n, const double* g_m, double* acc_v,
+                              double* acc_vc, const Ctl* ctl, int j_off, hipStream_t st)
+{
+    StepArgs<T> A;
+    // the wave's source coefficients cover its R harmonics plus 5 + 5 halo
+    // harmonics, one per lane
+    A.env = make_env(cs, sh, src, dst, s_n, g_m, acc_v, acc_vc, kWave - 10);
+    A.ctl = ctl;
+    A.j_off = j_off;
+    const int wpb = std::min(sh.waves_per_block, 4);
+    A.env.cgroup = wpb;
+    A.ntiles = fused3_tile_count(cs.ny, A.env.nchunks, wpb);
+    const int blocks = round_up8((A.ntiles + wpb - 1) / wpb);
+    hipLaunchKernelGGL(k_fused_step3<T>, dim3(blocks), dim3(wpb * kWave), 0, st, A);
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_fused_step2(const Consts& cs, const Shape& sh, Planes<T> src, Planes<T> dst,
                               const double* s_n, const double* g_m, double* acc_v,
                               double* acc_vc, const Ctl* ctl, int j_off, hipStream_t st)
@@ -265,6 +299,9 @@ hipError_t launch_reduce_obs(const Consts& cs, const T* a_h, const T* b_h, const
                                              const double*, const double*, double*, double*,   \
                                              const Ctl*, int, hipStream_t);                    \
     template hipError_t launch_fused_step2<T>(const Consts&, const Shape&, Planes<T>, Planes<T>, \
+                                              const double*, const double*, double*, double*,  \
+                                              const Ctl*, int, hipStream_t);                   \
+    template hipError_t launch_fused_step3<T>(const Consts&, const Shape&, Planes<T>, Planes<T>, \
                                               const double*, const double*, double*, double*,  \
                                               const Ctl*, int, hipStream_t);                   \
     template hipError_t launch_half_step<T>(const Consts&, const Shape&, T*, T*, const T*,      \

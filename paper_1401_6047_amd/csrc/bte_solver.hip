@@ -99,7 +99,8 @@ Layout make_layout(const bte_grid& g, int precision)
     Layout L;
     using namespace bte;
     int need = std::max({col_extent(g.n_y, kHalfCols, 1), col_extent(g.n_y, kFusedCols, 2),
-                         col_extent(g.n_y, kFused2Cols, 4), g.n_y + 2 * kPadCols});
+                         col_extent(g.n_y, kFused2Cols, 4), col_extent(g.n_y, kFused3Cols, 6),
+                         g.n_y + 2 * kPadCols});
     L.ld = (need + 63) / 64 * 64;
     L.rows = g.n_x + 2 * kPadRows;
     L.elem = precision == BTE_FP32_BULK ? 4 : 8;
@@ -230,7 +231,7 @@ bte_tuning default_tuning(const bte_grid& g)
 bte_status check_tuning(const bte_tuning& t)
 {
     if (t.kernel != BTE_KERNEL_FUSED && t.kernel != BTE_KERNEL_TWO_PASS &&
-        t.kernel != BTE_KERNEL_FUSED2)
+        t.kernel != BTE_KERNEL_FUSED2 && t.kernel != BTE_KERNEL_FUSED3)
         return fail(BTE_EINVAL, "unknown kernel form %d", t.kernel);
     if (t.rows_per_wave < 1 || t.rows_per_wave > kMaxRowsPerWave)
         return fail(BTE_EINVAL, "rows_per_wave must be in 1..%d", kMaxRowsPerWave);
@@ -242,7 +243,7 @@ bte_status check_tuning(const bte_tuning& t)
     return BTE_OK;
 }
 
-// Queue `count` (1 or 2) steps starting at step offset j_off.
+// Queue `count` (1, 2 or 3) steps starting at step offset j_off.
 template <typename T>
 hipError_t queue_steps_of(bte_solver* s, int j_off, int count, hipStream_t st)
 {
@@ -260,7 +261,10 @@ hipError_t queue_steps_of(bte_solver* s, int j_off, int count, hipStream_t st)
     }
     const int src = s->cur, dst = 1 - s->cur;
     hipError_t e;
-    if (count == 2)
+    if (count == 3)
+        e = bte::launch_fused_step3<T>(s->cs, sh, s->planes<T>(src), s->planes<T>(dst), s->s_n(),
+                                       s->g_m(), s->acc_v(), s->acc_vc(), s->ctl(), j_off, st);
+    else if (count == 2)
         e = bte::launch_fused_step2<T>(s->cs, sh, s->planes<T>(src), s->planes<T>(dst), s->s_n(),
                                        s->g_m(), s->acc_v(), s->acc_vc(), s->ctl(), j_off, st);
     else
@@ -274,7 +278,10 @@ hipError_t queue_steps_direct(bte_solver* s, int n, hipStream_t st)
 {
     int j = 0;
     while (j < n) {
-        const int count = (s->tune.kernel == BTE_KERNEL_FUSED2 && n - j >= 2) ? 2 : 1;
+        const int kf = s->tune.kernel;
+        const int count = (kf == BTE_KERNEL_FUSED3 && n - j >= 3) ? 3
+                          : ((kf == BTE_KERNEL_FUSED2 || kf == BTE_KERNEL_FUSED3) && n - j >= 2) ? 2
+                                                                                               : 1;
         hipError_t e = s->fp32() ? queue_steps_of<float>(s, j, count, st)
                                  : queue_steps_of<double>(s, j, count, st);
         if (e != hipSuccess) return e;

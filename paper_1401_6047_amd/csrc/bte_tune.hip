@@ -52,7 +52,7 @@ extern "C" bte_status bte_tune(const bte_grid* grid, const bte_params* params, v
         bte::set_last_error("best must not be NULL");
         return BTE_EINVAL;
     }
-    if (kernel_form < -1 || kernel_form > BTE_KERNEL_FUSED2) {
+    if (kernel_form < -1 || kernel_form > BTE_KERNEL_FUSED3) {
         bte::set_last_error("kernel_form must be -1 or a bte_kernel value");
         return BTE_EINVAL;
     }
@@ -84,19 +84,29 @@ extern "C" bte_status bte_tune(const bte_grid* grid, const bte_params* params, v
     n = std::max(n, std::max(G, 8));
     if (G > 0) n = (n + G - 1) / G * G;
 
-    const int rows[] = {2, 4, 6, 8, 12, 16, 24, 32, 48, 62};
+    // Harmonics per wave: for every chunk count c the smallest R that gives
+    // c chunks (R = ceil(n_x / c), the most even split).  How many tiles a
+    // launch has against how many waves the GPU holds at once decides how
+    // much of the last round of waves idles, so the whole range is timed.
+    std::vector<int> rows;
+    for (int c = 1; c <= grid->n_x; ++c) {
+        const int R = (grid->n_x + c - 1) / c;
+        if (R > 62) continue;
+        if (R < 2 && !rows.empty()) break;
+        if (rows.empty() || rows.back() != R) rows.push_back(std::max(R, 1));
+    }
     const int wpbs[] = {1, 2, 4, 8};
     bte_tuning win = base;
     double win_us = time_steps(s, base, n, st, ev);
-    for (int kernel = BTE_KERNEL_FUSED; kernel <= BTE_KERNEL_FUSED2; ++kernel) {
+    for (int kernel = BTE_KERNEL_FUSED; kernel <= BTE_KERNEL_FUSED3; ++kernel) {
         if (kernel_form >= 0 && kernel != kernel_form) continue;
         for (int R : rows) {
-            if (R > grid->n_x && R != rows[0]) continue;
             for (int w : wpbs) {
                 if (kernel == BTE_KERNEL_FUSED2 && (R > 58 || w > 4)) continue;
+                if (kernel == BTE_KERNEL_FUSED3 && (R > 54 || w > 4)) continue;
                 bte_tuning t{};
                 t.kernel = kernel;
-                t.rows_per_wave = std::min(R, grid->n_x);
+                t.rows_per_wave = R;
                 t.waves_per_block = w;
                 t.graph_steps = G;
                 const double us = time_steps(s, t, n, st, ev);

@@ -101,6 +101,11 @@ TUNINGS = [
     dict(kernel=2, rows_per_wave=5, waves_per_block=2, graph_steps=2),
     dict(kernel=2, rows_per_wave=58, waves_per_block=4, graph_steps=64),
     dict(kernel=2, rows_per_wave=13, waves_per_block=8, graph_steps=6),
+    dict(kernel=3),
+    dict(kernel=3, rows_per_wave=1, waves_per_block=1, graph_steps=0),
+    dict(kernel=3, rows_per_wave=7, waves_per_block=2, graph_steps=4),
+    dict(kernel=3, rows_per_wave=54, waves_per_block=4, graph_steps=64),
+    dict(kernel=3, rows_per_wave=62, waves_per_block=8, graph_steps=10),
 ]
 
 
@@ -131,7 +136,7 @@ RAGGED = [(2, 3), (3, 5), (5, 61), (7, 65), (9, 119), (33, 121), (17, 187), (64,
 
 
 @pytest.mark.parametrize("nx,ny", RAGGED)
-@pytest.mark.parametrize("kernel", [0, 1, 2])
+@pytest.mark.parametrize("kernel", [0, 1, 2, 3])
 def test_ragged_grids_random_state(bte, nx, ny, kernel):
     w = W.random_params(1000 + nx * 7 + ny, nx=nx, ny=ny, phi=6.0, dt=2e-3)
     a, b = W.smooth_state(nx * 31 + ny, nx, ny, phi=6.0)
@@ -189,7 +194,7 @@ def test_graph_and_direct_launches_agree_bitwise(bte):
     two-pass form give the same FP64 bits (same arithmetic per cell)."""
     w = W.random_params(5, nx=24, ny=200, dt=1e-3)
     outs = []
-    for kern in (0, 2, 1):
+    for kern in (0, 2, 1, 3):
         for g in (0, 2, 32):
             _, st = run_gpu(bte, w, 97, tuning=dict(kernel=kern, graph_steps=g))
             outs.append(st)
@@ -290,4 +295,4 @@ def test_autotuner_returns_valid_shape_with_identical_results(bte):
     for x, y in zip(tuned, ref):
         np.testing.assert_array_equal(x, y)
     with pytest.raises(bte.BteError):
-        bte.bte_tune(s.grid, s.params, 0, 0, 0, kernel_form=5)
+        bte.bte_tune(s.grid, s.params, 0, 0, 0, kernel_form=7)
