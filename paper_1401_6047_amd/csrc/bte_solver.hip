@@ -224,7 +224,9 @@ bte_tuning default_tuning(const bte_grid& g)
     t.rows_per_wave = std::min(R, g.n_x);
     t.waves_per_block = 1;
     const double cells = static_cast<double>(g.n_x) * g.n_y;
-    t.graph_steps = cells < 4e6 ? 64 : 16;
+    // a multiple of 6, so that a graph holds only two-step or only
+    // three-step launches (no one-step remainder inside a replay)
+    t.graph_steps = cells < 4e6 ? 96 : 48;
     return t;
 }
 

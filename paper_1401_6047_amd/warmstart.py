@@ -22,6 +22,7 @@ from __future__ import annotations
 import argparse
 import json
 import math
+import os
 import time
 
 import numpy as np
@@ -142,16 +143,86 @@ def run(n_train, n_test, epochs, seed=W.SWEEP_SEED, train_nx=48, eval_nx=128, lo
     }
 
 
+def save_network(net, path):
+    """Parameters and normalisation of a trained network (numpy .npz)."""
+    np.savez(path, params=net.params().cpu().numpy(), norm=net.normalization())
+
+
+def load_network(path, max_batch=512):
+    d = np.load(path)          # plain arrays, no pickled objects
+    net = M.Mlp(max_batch=max_batch, precision=M.BTE_MLP_BF16)
+    net.set_params(d["params"])
+    net.set_normalization(d["norm"])
+    return net
+
+
+def run_one(mode, n_test, n_train=32768, epochs=60, seed=W.SWEEP_SEED, net_path="",
+            eval_nx=128, log=print):
+    """One side of the comparison on the held-out draws: mode "cold" (from
+    f0) or "warm" (network trained here on n_train coarse states, or loaded
+    from net_path).  Returns per-instance results and timings."""
+    import torch
+    stamp = time.perf_counter()
+
+    def say(msg):
+        if log:
+            log(f"[{time.perf_counter() - stamp:7.1f} s] {msg}", flush=True)
+
+    out = {"mode": mode, "instances": n_test}
+    test = W.sweep_draws(n_test, seed=seed + 3, nx=eval_nx)
+    pred, infer = None, 0.0
+    if mode == "warm":
+        if net_path and os.path.exists(net_path):
+            net = load_network(net_path)
+            out["network"] = {"loaded": net_path}
+        else:
+            train = coarse_draws(n_train, seed + 1)
+            say(f"training sweep: {n_train} instances")
+            tres, states, tsecs = sweep_states(train, train[0].nx, 10.0, train[0].dt, log=log)
+            ok = [i for i, r in enumerate(tres) if r["converged"] == 1]
+            keep = torch.as_tensor(ok, device="cuda")
+            feats = M.features_of([train[i] for i in ok])
+            net, hist, secs = train_network(feats, states.index_select(0, keep).contiguous(),
+                                            epochs, seed=seed + 2, log=log)
+            say(f"trained {epochs} epochs in {secs:.1f} s: loss {hist[0]:.3e} -> {hist[-1]:.3e}")
+            out["network"] = {"train_instances": n_train, "converged": len(ok),
+                              "sweep_s": tsecs, "epochs": epochs, "train_s": secs,
+                              "loss_last_epoch": hist[-1]}
+            if net_path:
+                save_network(net, net_path)
+        t0 = time.perf_counter()
+        pred = net.predict(M.features_of(test))
+        torch.cuda.synchronize()
+        infer = time.perf_counter() - t0
+        net.close()
+    say(f"{mode} sweep of {n_test} instances")
+    res, secs = sweep(test, eval_nx, 10.0, test[0].dt, warm=pred, log=log)
+    say(f"  {secs:.1f} s")
+    cells = [eval_nx * w.ny for w in test]
+    out.update(wall_s=secs, inference_s=infer,
+               cell_steps=float(sum(c * r["steps"] for c, r in zip(cells, res))),
+               results=[dict(r, E_dc=w.E_dc, B=w.B, omega=w.omega, mu=w.mu)
+                        for w, r in zip(test, res)])
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--train", type=int, default=4096)
     ap.add_argument("--test", type=int, default=512)
     ap.add_argument("--epochs", type=int, default=60)
+    ap.add_argument("--mode", choices=("both", "cold", "warm"), default="both",
+                    help="both: train, then cold and warm sweeps; cold / warm: one side only")
+    ap.add_argument("--net", default="", help="save the trained network here (warm), or load it")
     ap.add_argument("--out", default="")
     a = ap.parse_args()
-    res = run(a.train, a.test, a.epochs)
+    if a.mode == "both":
+        res = run(a.train, a.test, a.epochs)
+    else:
+        res = run_one(a.mode, a.test, a.train, a.epochs, net_path=a.net)
     line = json.dumps(res)
-    print(line, flush=True)
+    print(line if a.mode == "both" else json.dumps({k: v for k, v in res.items() if k != "results"}),
+          flush=True)
     if a.out:
         with open(a.out, "w") as f:
             f.write(line + "\n")
