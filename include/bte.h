@@ -215,6 +215,9 @@ typedef struct {
     double tol;             /* absolute |A_p - A_{p-1}| threshold, > 0 */
     int32_t min_periods;    /* >= 2 */
     int32_t max_periods;    /* >= min_periods */
+    int32_t confirm;        /* consecutive periods that must each change A by less than
+                               tol before an instance stops (>= 1; 1 = the single test) */
+    int32_t reserved;       /* must be 0 */
 } bte_batch_config;
 
 typedef struct {

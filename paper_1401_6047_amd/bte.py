@@ -65,7 +65,8 @@ class bte_batch_config(ctypes.Structure):
                 ("phiy_min", ctypes.c_double), ("phiy_max", ctypes.c_double),
                 ("dt", ctypes.c_double), ("alpha", ctypes.c_double),
                 ("tol", ctypes.c_double), ("min_periods", ctypes.c_int32),
-                ("max_periods", ctypes.c_int32)]
+                ("max_periods", ctypes.c_int32), ("confirm", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class bte_batch_tuning(ctypes.Structure):
@@ -355,7 +356,7 @@ class Solver:
     def tuning(self) -> bte_tuning:
         return bte_get_tuning(self.handle)
 
-    def run_periods(self, tol=1e-6, min_periods=2, max_periods=400):
+    def run_periods(self, tol=1e-6, min_periods=2, max_periods=400, confirm=1):
         """Advance whole ac periods from a fresh solver (step 0 = phase 0) until
         the per-period absorption (bte_obs.absorption_cov) changes by less than
         `tol` between consecutive periods: the batched sweep's criterion, period
@@ -363,7 +364,7 @@ class Solver:
         shaped like the entries of Batch.results()."""
         import math
         L = max(1, int(round(2.0 * math.pi / (self.params.omega * self.params.dt))))
-        k, p, prev = 0, 0, None
+        k, p, prev, run_ok = 0, 0, None, 0
         out = dict(absorption=0.0, v_avg=0.0, dA=0.0, steps=0, periods=0, converged=0,
                    status=BTE_OK)
         while True:
@@ -378,7 +379,8 @@ class Solver:
                        status=int(o.status))
             if o.status != BTE_OK or not math.isfinite(o.absorption_cov):
                 break
-            if p >= min_periods and p > 1 and dA < tol:
+            run_ok = run_ok + 1 if (p > 1 and dA < tol) else 0
+            if p >= min_periods and run_ok >= confirm:
                 out["converged"] = 1
                 break
             if p >= max_periods:
@@ -411,10 +413,10 @@ class Solver:
 
 
 def make_batch_config(n_x, phiy_min, phiy_max, dt, precision=BTE_FP64, alpha=1.0, tol=1e-6,
-                      min_periods=2, max_periods=200) -> bte_batch_config:
+                      min_periods=2, max_periods=200, confirm=1) -> bte_batch_config:
     return bte_batch_config(int(n_x), int(precision), float(phiy_min), float(phiy_max),
                             float(dt), float(alpha), float(tol), int(min_periods),
-                            int(max_periods))
+                            int(max_periods), int(confirm), 0)
 
 
 class Batch:

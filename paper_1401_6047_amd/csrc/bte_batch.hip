@@ -62,7 +62,7 @@ struct BatchArgs {
     int R;                    // harmonics per wave
     int form;                 // BTE_KERNEL_FUSED or BTE_KERNEL_FUSED2
     double tol;
-    int min_periods, max_periods;
+    int min_periods, max_periods, confirm;
 };
 
 __global__ void k_batch_reset(int32_t* queue)
@@ -229,7 +229,7 @@ __global__ __launch_bounds__(kMaxWavesPerGroup * kWave) void k_batch(BatchArgs<T
         E.cgroup = nwaves;
         const int tiles2 = fused2_tile_count(I.ny, n2, nwaves);
         int64_t k = 0;
-        int cur = 0, p = 0, converged = 0;
+        int cur = 0, p = 0, converged = 0, run_ok = 0;
         int32_t status = BTE_OK;
         double A_prev = 0.0, A_p = 0.0, v_p = 0.0, dA = 0.0;
         while (true) {
@@ -294,7 +294,11 @@ __global__ __launch_bounds__(kMaxWavesPerGroup * kWave) void k_batch(BatchArgs<T
                 status = BTE_EUNSTABLE;
                 break;
             }
-            if (p >= B.min_periods && p > 1 && dA < B.tol) {
+            // a run of `confirm` consecutive small changes: a transient that
+            // rotates (complex eigenvalues of the period map) can make two
+            // periods agree by accident while both are still off
+            run_ok = (p > 1 && dA < B.tol) ? run_ok + 1 : 0;
+            if (p >= B.min_periods && run_ok >= B.confirm) {
                 converged = 1;
                 break;
             }
@@ -428,6 +432,8 @@ bte_status validate_batch(const bte_batch_config* c, int n, const bte_instance* 
         return bfail(BTE_EINVAL, "unknown precision");
     if (c->min_periods < 2 || c->max_periods < c->min_periods)
         return bfail(BTE_EINVAL, "need 2 <= min_periods <= max_periods");
+    if (c->confirm < 1 || c->confirm > 64) return bfail(BTE_EINVAL, "confirm must be in 1..64");
+    if (c->reserved != 0) return bfail(BTE_EINVAL, "reserved must be 0");
     if (t) {
         if (t->kernel != BTE_KERNEL_FUSED && t->kernel != BTE_KERNEL_FUSED2)
             return bfail(BTE_EINVAL, "batch kernel must be FUSED or FUSED2");
@@ -507,6 +513,7 @@ hipError_t capture_batch(bte_batch* b)
     A.tol = b->cfg.tol;
     A.min_periods = b->cfg.min_periods;
     A.max_periods = b->cfg.max_periods;
+    A.confirm = b->cfg.confirm;
     hipLaunchKernelGGL(bte::k_batch_reset, dim3(1), dim3(64), 0, b->capture_stream, A.queue);
     hipLaunchKernelGGL(bte::k_batch<T>, dim3(b->L.groups), dim3(b->tune.waves_per_group * bte::kWave),
                        0, b->capture_stream, A);

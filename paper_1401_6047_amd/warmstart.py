@@ -33,12 +33,12 @@ from . import workloads as W
 
 
 def sweep_states(instances, nx, phiy, dt, precision=bte.BTE_FP32_BULK, tol=1e-6,
-                 max_periods=400, log=None):
+                 max_periods=400, log=None, confirm=1):
     """Run a batched sweep to convergence; return (results, states (n,64,128)
     CUDA tensor, wall seconds)."""
     import torch
     cfg = bte.make_batch_config(nx, -phiy, phiy, dt, precision=precision, tol=tol,
-                                min_periods=2, max_periods=max_periods)
+                                min_periods=2, max_periods=max_periods, confirm=confirm)
     b = bte.Batch(cfg, instances)
     out = torch.zeros((len(instances), 64, 128), dtype=torch.float32, device="cuda")
     b.set_state_output(out)
@@ -49,10 +49,10 @@ def sweep_states(instances, nx, phiy, dt, precision=bte.BTE_FP32_BULK, tol=1e-6,
 
 
 def sweep(instances, nx, phiy, dt, warm=None, precision=bte.BTE_FP32_BULK, tol=1e-6,
-          max_periods=400, log=None):
+          max_periods=400, log=None, confirm=1):
     """Run a batched sweep (cold, or warm from coefficients); (results, seconds)."""
     cfg = bte.make_batch_config(nx, -phiy, phiy, dt, precision=precision, tol=tol,
-                                min_periods=2, max_periods=max_periods)
+                                min_periods=2, max_periods=max_periods, confirm=confirm)
     b = bte.Batch(cfg, instances)
     b.set_warm_start(warm)
     secs = b.run(log=log)
@@ -157,7 +157,7 @@ def load_network(path, max_batch=512):
 
 
 def run_one(mode, n_test, n_train=32768, epochs=60, seed=W.SWEEP_SEED, net_path="",
-            eval_nx=128, log=print):
+            eval_nx=128, log=print, confirm=1):
     """One side of the comparison on the held-out draws: mode "cold" (from
     f0) or "warm" (network trained here on n_train coarse states, or loaded
     from net_path).  Returns per-instance results and timings."""
@@ -168,7 +168,7 @@ def run_one(mode, n_test, n_train=32768, epochs=60, seed=W.SWEEP_SEED, net_path=
         if log:
             log(f"[{time.perf_counter() - stamp:7.1f} s] {msg}", flush=True)
 
-    out = {"mode": mode, "instances": n_test}
+    out = {"mode": mode, "instances": n_test, "confirm": confirm}
     test = W.sweep_draws(n_test, seed=seed + 3, nx=eval_nx)
     pred, infer = None, 0.0
     if mode == "warm":
@@ -196,7 +196,7 @@ def run_one(mode, n_test, n_train=32768, epochs=60, seed=W.SWEEP_SEED, net_path=
         infer = time.perf_counter() - t0
         net.close()
     say(f"{mode} sweep of {n_test} instances")
-    res, secs = sweep(test, eval_nx, 10.0, test[0].dt, warm=pred, log=log)
+    res, secs = sweep(test, eval_nx, 10.0, test[0].dt, warm=pred, log=log, confirm=confirm)
     say(f"  {secs:.1f} s")
     cells = [eval_nx * w.ny for w in test]
     out.update(wall_s=secs, inference_s=infer,
@@ -214,12 +214,14 @@ def main():
     ap.add_argument("--mode", choices=("both", "cold", "warm"), default="both",
                     help="both: train, then cold and warm sweeps; cold / warm: one side only")
     ap.add_argument("--net", default="", help="save the trained network here (warm), or load it")
+    ap.add_argument("--confirm", type=int, default=1,
+                    help="consecutive small period-to-period changes required to stop")
     ap.add_argument("--out", default="")
     a = ap.parse_args()
     if a.mode == "both":
         res = run(a.train, a.test, a.epochs)
     else:
-        res = run_one(a.mode, a.test, a.train, a.epochs, net_path=a.net)
+        res = run_one(a.mode, a.test, a.train, a.epochs, net_path=a.net, confirm=a.confirm)
     line = json.dumps(res)
     print(line if a.mode == "both" else json.dumps({k: v for k, v in res.items() if k != "results"}),
           flush=True)

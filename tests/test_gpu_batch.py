@@ -42,10 +42,10 @@ def oracle_periods(w, P):
     return out
 
 
-def make_batch(bte, inst, precision=0, tuning=None, tol=1e-6, max_periods=60, **kw):
+def make_batch(bte, inst, precision=0, tuning=None, tol=1e-6, max_periods=60, confirm=1, **kw):
     w0 = inst[0]
     cfg = bte.make_batch_config(w0.nx, w0.phiy_min, w0.phiy_max, w0.dt, precision=precision,
-                                tol=tol, min_periods=2, max_periods=max_periods)
+                                tol=tol, min_periods=2, max_periods=max_periods, confirm=confirm)
     return bte.Batch(cfg, inst, tuning=tuning, **kw)
 
 
@@ -177,3 +177,15 @@ def test_zero_warm_start_is_cold_start_and_good_warm_start_saves_periods(bte, sm
         assert wr["periods"] <= c["periods"]
         assert abs(wr["absorption"] - c["absorption"]) < 1e-6 + 2.0 * abs(c["absorption"]) / K
     assert sum(w["periods"] for w in warm) < sum(c["periods"] for c in cold)
+
+
+def test_batch_confirm_requires_consecutive_small_changes(bte, small, small_ref):
+    """With confirm = 2 an instance stops at the first period p whose change
+    and the previous period's change are both below tol (oracle periods)."""
+    res = run_batch(bte, small, confirm=2)
+    for w, r, ref in zip(small, res, small_ref):
+        d = [abs(ref[p][0] - ref[p - 1][0]) for p in range(1, len(ref))]   # d[k] = |A_{k+2} - A_{k+1}|
+        want = next(p + 2 for p in range(1, len(d)) if d[p] < 1e-6 and d[p - 1] < 1e-6)
+        assert r["converged"] == 1 and r["periods"] == want, (w.name, r, want)
+        A, v, pend = ref[want - 1]
+        assert relerr(r["absorption"], A, 1e-2 * w.E_w) < 1e-10
