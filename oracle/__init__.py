@@ -5,8 +5,10 @@ import this package.  The product path (the HIP library and its Python
 binding) never imports, links or calls anything here, and nothing here
 imports the product package.
 
-The arithmetic lives in ``bte_oracle.c`` (plain C, FP64, OpenMP over phi_y);
-this module only marshals numpy arrays into it.  ``build()`` compiles it with
+The arithmetic lives in ``bte_oracle.c`` (plain C, FP64, OpenMP over phi_y)
+and ``characteristics.c`` (the same physics by characteristic curves, Sec. 4);
+this module only marshals numpy arrays into them, apart from the quadrature
+nodes of the equilibrium average below.  ``build()`` compiles it with
 gcc.  See the header of ``bte_oracle.c`` for what is computed and which
 passages of the paper each part follows.
 """
@@ -20,7 +22,7 @@ from dataclasses import dataclass
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "bte_oracle.c")
+_SRC = [os.path.join(_HERE, "bte_oracle.c"), os.path.join(_HERE, "characteristics.c")]
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 # No -march=native: the library is built here and may run on another host.
@@ -33,7 +35,7 @@ def build(force: bool = True) -> str:
     """Compile the oracle into ``oracle/liboracle.so`` and return its path."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
-        cmd = ["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm"]
+        cmd = ["gcc", *CFLAGS, "-o", tmp, *_SRC, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, _LIB)
     return _LIB
@@ -68,6 +70,10 @@ def _load():
         lib.oracle_run.restype = ctypes.c_int
         lib.oracle_equilibrium.argtypes = [ctypes.POINTER(_Params), dp]
         lib.oracle_equilibrium.restype = ctypes.c_int
+        lib.oracle_characteristic_v.argtypes = [
+            ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
+            dp, dp, dp, ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_int32, dp]
+        lib.oracle_characteristic_v.restype = ctypes.c_int
         lib.oracle_max_threads.argtypes = []
         lib.oracle_max_threads.restype = ctypes.c_int
         _lib = lib
@@ -178,3 +184,64 @@ def run(pb: Problem, n_steps: int, *, window: tuple[int, int] = (0, 0),
 
 def max_threads() -> int:
     return int(_load().oracle_max_threads())
+
+
+# ---------------------------------------------------------------------------
+# Characteristic curves (Sec. 4): pendulum flow with exponential memory.
+# ---------------------------------------------------------------------------
+def equilibrium_nodes(mu: float | None, n: int = 12):
+    """Nodes and weights of the average over the equilibrium distribution of
+    Sec. 2 (density proportional to exp(mu cos phi_x - mu phi_y^2 / 2)).
+
+    ``mu`` None is the zero-temperature limit: one node at the origin.
+    Otherwise an n x n Gauss-Hermite product rule in units of 1/sqrt(mu):
+    exact in phi_y (a Gaussian), and in phi_x the factor
+    exp(mu (cos x - 1 + x^2/2)) is folded into the weights.  The phi_x rule
+    ignores the periodic images of the peak, so it is meant for large mu
+    (narrow peak); the nodes must stay inside |phi_x| < pi/2.
+    """
+    if mu is None:
+        return np.zeros(1), np.zeros(1), np.ones(1)
+    t, wt = np.polynomial.hermite.hermgauss(int(n))
+    s = np.sqrt(2.0 / mu)
+    x = s * t
+    if np.abs(x).max() >= np.pi / 2:
+        raise ValueError("equilibrium_nodes: peak too wide for the Gauss-Hermite rule")
+    wx = wt * np.exp(mu * (np.cos(x) - 1.0 + 0.5 * x * x))
+    wx /= wx.sum()
+    wy = wt / wt.sum()
+    X, Y = np.meshgrid(x, s * t, indexing="ij")
+    return X.ravel().copy(), Y.ravel().copy(), np.outer(wx, wy).ravel().copy()
+
+
+def characteristic_v(E_dc: float, E_w: float, omega: float, B: float, mu: float | None,
+                     *, h: float = 0.01, tau_max: float = 36.0, nodes: int = 12,
+                     n_threads: int = 0):
+    """v_dr(t_i) of the periodic state on t_i = i*h', i < n, with n h' one
+    field period (h' is the largest step <= h that divides the period); for
+    E_w = 0 one value.  Returns (t, v)."""
+    x0, y0, w = equilibrium_nodes(mu, nodes)
+    if E_w != 0.0:
+        period = 2.0 * np.pi / omega
+        n = int(np.ceil(period / h))
+        hh = period / n
+    else:
+        n, hh = 1, h
+    v = np.zeros(n)
+    rc = _load().oracle_characteristic_v(float(E_dc), float(E_w), float(omega), float(B),
+                                         len(w), _ptr(x0), _ptr(y0), _ptr(w), n, hh,
+                                         float(tau_max), int(n_threads), _ptr(v))
+    if rc != 0:
+        raise ValueError(f"oracle_characteristic_v failed ({rc})")
+    return np.arange(n) * hh, v
+
+
+def characteristic_absorption(E_dc: float, E_w: float, omega: float, B: float,
+                              mu: float | None, **kw) -> float:
+    """A = <(2 I_0/I_1) v_dr(t) cos(omega t)>_t over one period of the
+    periodic state (Sec. 2); I_0/I_1 -> 1 in the zero-temperature limit.
+    The period mean of a sampled periodic function is the plain mean of
+    equally spaced samples."""
+    t, v = characteristic_v(E_dc, E_w, omega, B, mu, **kw)
+    r = 1.0 if mu is None else 1.0 / bessel_ratios(mu, 1)[1]
+    return float(2.0 * r * np.mean(v * np.cos(omega * t)))
