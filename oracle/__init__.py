@@ -245,3 +245,27 @@ def characteristic_absorption(E_dc: float, E_w: float, omega: float, B: float,
     t, v = characteristic_v(E_dc, E_w, omega, B, mu, **kw)
     r = 1.0 if mu is None else 1.0 / bessel_ratios(mu, 1)[1]
     return float(2.0 * r * np.mean(v * np.cos(omega * t)))
+
+
+# ---------------------------------------------------------------------------
+# The distribution function from its Fourier coefficients (Sec. 2).
+# ---------------------------------------------------------------------------
+def reconstruct(a: np.ndarray, b: np.ndarray, n_phix: int,
+                cols: np.ndarray | None = None, rows: np.ndarray | None = None) -> np.ndarray:
+    """f(x_j, phi_y(m)) = sum_n a_n(m) cos(n x_j) + b_n(m) sin(n x_j) (Eq.
+    f_fourier) on x_j = -pi + 2 pi j / n_phix; b_0 is taken as zero.
+
+    a, b: [N_x, N_y] arrays.  Returns [n_phix, N_y], or only the samples
+    (rows[i], cols[i]) when both index arrays are given."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.array(b, dtype=np.float64)
+    b[0] = 0.0
+    n = np.arange(a.shape[0])
+    if rows is not None and cols is not None:
+        x = -np.pi + 2.0 * np.pi * np.asarray(rows) / n_phix
+        ang = np.outer(x, n)
+        return np.einsum("in,ni->i", np.cos(ang), a[:, cols]) + \
+            np.einsum("in,ni->i", np.sin(ang), b[:, cols])
+    x = -np.pi + 2.0 * np.pi * np.arange(n_phix) / n_phix
+    ang = np.outer(x, n)
+    return np.cos(ang) @ a + np.sin(ang) @ b

@@ -553,3 +553,42 @@ def test_small_signal_absorption_matches_linear_response():
     # the ac part is a large share of A here, so the check sees the response
     A_ac = (2.0 / ratio) * np.mean(E_w * np.real(dv * np.exp(1j * omega * tk)) * np.cos(omega * tk))
     assert abs(A_ac) > 0.5 * abs(A_pred)
+
+
+# ---------------------------------------------------------------------------
+# f(phi_x, phi_y) from the coefficients (Eq. f_fourier).
+# ---------------------------------------------------------------------------
+def test_reconstruct_equilibrium_is_the_boltzmann_distribution():
+    """The equilibrium coefficients summed back give f0 of Sec. 2 in closed
+    form, exp(mu cos phi_x - mu phi_y^2/2) sqrt(mu/(2 pi alpha))/(2 pi I0)."""
+    for mu, nx in ((1.0, 24), (10.0, 48), (116.0, 120)):
+        pb = oracle.Problem(nx=nx, ny=41, phiy_min=-2, phiy_max=2, E_dc=0, E_w=0, omega=0, B=0,
+                            mu=mu, dt=1e-3, alpha=0.9496)
+        f = oracle.reconstruct(oracle.equilibrium(pb), np.zeros((nx, pb.ny)), 97)
+        x = -np.pi + 2 * np.pi * np.arange(97) / 97
+        y = grid(pb)
+        ref = (np.exp(mu * (np.cos(x) - 1))[:, None] * np.exp(-0.5 * mu * y * y)[None, :]
+               * math.sqrt(mu / (2 * math.pi * pb.alpha)) / (2 * math.pi * sp.ive(0, mu)))
+        np.testing.assert_allclose(f, ref, rtol=0, atol=1e-13 * ref.max())
+
+
+def test_reconstruct_inverts_by_fft():
+    """With n_phix >= 2 N_x samples the DFT of f along phi_x returns the
+    coefficients: F_0 = M a_0, F_k = (M/2)(-1)^k (a_k - i b_k)."""
+    g = np.random.Generator(np.random.PCG64(7))
+    nx, ny, M = 16, 5, 40
+    a = g.standard_normal((nx, ny))
+    b = g.standard_normal((nx, ny))
+    F = np.fft.fft(oracle.reconstruct(a, b, M), axis=0)
+    k = np.arange(1, nx)
+    sgn = ((-1.0) ** k)[:, None]
+    np.testing.assert_allclose(F[0].real / M, a[0], atol=1e-13)
+    np.testing.assert_allclose(2 * sgn * F[1:nx].real / M, a[1:], atol=1e-13)
+    np.testing.assert_allclose(-2 * sgn * F[1:nx].imag / M, b[1:], atol=1e-13)
+    # b_0 is not part of the series
+    b2 = b.copy(); b2[0] = 99.0
+    np.testing.assert_array_equal(oracle.reconstruct(a, b2, M), oracle.reconstruct(a, b, M))
+    # sampled form agrees with the full array
+    rows, cols = np.array([0, 7, 39]), np.array([4, 0, 2])
+    np.testing.assert_allclose(oracle.reconstruct(a, b, M, cols=cols, rows=rows),
+                               oracle.reconstruct(a, b, M)[rows, cols], rtol=0, atol=1e-13)
