@@ -29,6 +29,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, HERE)
 
 HBM_PEAK_GBS = 8000.0
+# FP64 vector FMA rate of the MI355X (256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz)
+FP64_PEAK_TFLOPS = 78.6
 
 # Algorithmic bytes per cell and launch: the fused kernels read and write the
 # four state values of both grids once per launch (8 values; the two-step
@@ -120,6 +122,33 @@ def time_solver(bte, torch, w, precision, kernel, steps, warmup, autotune=True, 
     }
     s.close()
     return out
+
+
+def reconstruct_bench(bte, torch, w, n_phix=512, launches=20):
+    """f(phi_x, phi_y) reconstruction (Eq. f_fourier) of the workload's state
+    on n_phix phi_x samples: average launch time by HIP events on the
+    solver's stream, against the FP64 vector FMA rate (the direct sum does
+    two FMAs per sample, phi_y point and harmonic n >= 1)."""
+    s = bte.Solver.from_workload(w)
+    out = torch.empty((n_phix, w.ny), dtype=torch.float64, device="cuda")
+    for _ in range(3):
+        s.reconstruct(n_phix, out)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record(s.stream)
+    for _ in range(launches):
+        s.reconstruct(n_phix, out)
+    stop.record(s.stream)
+    torch.cuda.synchronize()
+    s.close()
+    us = start.elapsed_time(stop) * 1e3 / launches
+    flops = 4.0 * (w.nx - 1) * n_phix * w.ny
+    tf = flops / (us * 1e-6) / 1e12
+    return {"workload": f"{w.name} state, {n_phix} phi_x samples", "kernel": "k_reconstruct",
+            "avg_launch_us": us, "flops_per_launch": flops,
+            "roofline": {"bound": "alu", "achieved": tf, "peak": FP64_PEAK_TFLOPS,
+                         "unit": "TFLOP/s", "frac": tf / FP64_PEAK_TFLOPS}}
 
 
 def main_run_form(run):
@@ -325,6 +354,8 @@ def main():
                                                       "achieved_GBs", "avg_launch_us", "kernel",
                                                       "tuning")}
                             for k, v in variants.items()}
+    if not args.no_variants:
+        line["reconstruct"] = reconstruct_bench(bte, torch, w)
     if args.copy_mib > 0:
         # a plain device-to-device copy of known size, for scaling the HBM
         # traffic counters of the step kernel

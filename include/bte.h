@@ -182,6 +182,35 @@ bte_status bte_tune(const bte_grid* grid, const bte_params* params, void* worksp
                     double target_ms, bte_tuning* best, double* best_us_per_step);
 
 /* ------------------------------------------------------------------------ */
+/* The distribution function itself                                         */
+/* ------------------------------------------------------------------------ */
+/* f(phi_x, phi_y) from Fourier coefficients (Sec. 2, Eq. f_fourier), on the
+   uniform phi_x grid x_j = -pi + 2 pi j / n_phix, j = 0 .. n_phix-1 (the
+   first Brillouin zone, right end excluded) at every phi_y point:
+
+       out[j * n_y + m] = sum_{n < N_x} a_n(m) cos(n x_j) + b_n(m) sin(n x_j).
+
+   `out` is a device array of n_phix * n_y doubles, owned by the caller and
+   fully overwritten (rows are phi_x samples, phi_y contiguous).  Direct sum in
+   FP64; every term's angle is reduced exactly from the integer phase
+   (n j mod n_phix) / n_phix.  Any n_phix >= 1 is accepted (n_phix < 2 N_x
+   samples alias harmonics, as any sampling does).  Queued on the stream;
+   nothing is synchronised or allocated.
+   Errors: BTE_EINVAL for NULL pointers, a misaligned `out` (8 bytes),
+   n_phix outside 1 .. 2^20, or bad sizes. */
+
+/* The solver's whole-grid state (step k).  FP32-bulk solvers' coefficients
+   are widened to FP64.  Queued on the solver's stream after all work queued
+   before it. */
+bte_status bte_reconstruct(bte_solver* s, int32_t n_phix, double* out);
+
+/* Caller coefficients: device arrays a and b of N_x rows of `ld` >= n_y
+   doubles each (row n holds a_n or b_n at m = 0 .. n_y-1); row 0 of b is
+   not read (b_0 = 0).  Queued on `hip_stream` (a hipStream_t, or NULL). */
+bte_status bte_reconstruct_coeffs(const double* a, const double* b, int32_t n_x, int32_t n_y,
+                                  int64_t ld, int32_t n_phix, double* out, void* hip_stream);
+
+/* ------------------------------------------------------------------------ */
 /* Batched parameter sweeps                                                  */
 /* ------------------------------------------------------------------------ */
 /* Many independent instances (each its own fields, temperature and phi_y

@@ -110,6 +110,9 @@ def _load():
         "bte_get_tuning": ([vp, P(bte_tuning)], ctypes.c_int),
         "bte_tune": ([P(bte_grid), P(bte_params), vp, ctypes.c_size_t, vp, ctypes.c_int32,
                       ctypes.c_double, P(bte_tuning), dp], ctypes.c_int),
+        "bte_reconstruct": ([vp, ctypes.c_int32, vp], ctypes.c_int),
+        "bte_reconstruct_coeffs": ([vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
+                                    ctypes.c_int32, vp, vp], ctypes.c_int),
         "bte_batch_workspace_bytes": ([P(bte_batch_config), ctypes.c_int32, P(bte_instance),
                                        P(bte_batch_tuning), P(ctypes.c_size_t)], ctypes.c_int),
         "bte_batch_create": ([P(bte_batch_config), ctypes.c_int32, P(bte_instance),
@@ -195,6 +198,42 @@ def bte_get_state(h: int, a_h=None, b_h=None, a_f=None, b_f=None):
 def bte_set_state(h: int, a_h, b_h, a_f=None, b_f=None, step: int = 0):
     _check(_lib.bte_set_state(ctypes.c_void_p(h), _dptr(a_h), _dptr(b_h), _dptr(a_f), _dptr(b_f),
                               int(step)), "bte_set_state")
+
+
+def bte_reconstruct(h: int, n_phix: int, out_ptr: int):
+    _check(_lib.bte_reconstruct(ctypes.c_void_p(h), int(n_phix), ctypes.c_void_p(out_ptr or None)),
+           "bte_reconstruct")
+
+
+def bte_reconstruct_coeffs(a_ptr: int, b_ptr: int, n_x: int, n_y: int, ld: int, n_phix: int,
+                           out_ptr: int, stream_ptr: int):
+    _check(_lib.bte_reconstruct_coeffs(ctypes.c_void_p(a_ptr or None), ctypes.c_void_p(b_ptr or None),
+                                       int(n_x), int(n_y), int(ld), int(n_phix),
+                                       ctypes.c_void_p(out_ptr or None),
+                                       ctypes.c_void_p(stream_ptr or None)),
+           "bte_reconstruct_coeffs")
+
+
+def reconstruct(a, b, n_phix: int, out=None, stream=None):
+    """f(phi_x_j, phi_y_m) from FP64 CUDA coefficient tensors a, b of shape
+    (N_x, N_y) (rows may be strided; elements contiguous) on the uniform
+    phi_x grid x_j = -pi + 2 pi j / n_phix.  Returns (n_phix, N_y) float64."""
+    import torch
+    for t in (a, b):
+        if t.dtype != torch.float64 or not t.is_cuda or t.dim() != 2 or t.stride(1) != 1:
+            raise ValueError("a and b must be 2-D float64 CUDA tensors with contiguous rows")
+    if a.shape != b.shape or a.stride(0) != b.stride(0):
+        raise ValueError("a and b must have the same shape and row stride")
+    nx, ny = a.shape
+    if out is None:
+        out = torch.empty((n_phix, ny), dtype=torch.float64, device=a.device)
+    elif (out.dtype != torch.float64 or tuple(out.shape) != (n_phix, ny) or
+          not out.is_contiguous()):
+        raise ValueError("out must be a contiguous float64 tensor of shape (n_phix, N_y)")
+    st = stream if stream is not None else torch.cuda.current_stream(a.device)
+    bte_reconstruct_coeffs(a.data_ptr(), b.data_ptr(), nx, ny, a.stride(0), n_phix,
+                           out.data_ptr(), st.cuda_stream)
+    return out
 
 
 def bte_set_tuning(h: int, t: bte_tuning):
@@ -386,6 +425,20 @@ class Solver:
             if p >= max_periods:
                 break
             prev = o.absorption_cov
+        return out
+
+    def reconstruct(self, n_phix: int, out=None):
+        """f(phi_x, phi_y) of the current whole-grid state on x_j = -pi +
+        2 pi j / n_phix: a (n_phix, N_y) float64 tensor on this solver's
+        device, filled on its stream."""
+        import torch
+        ny = self.grid.n_y
+        if out is None:
+            out = torch.empty((n_phix, ny), dtype=torch.float64, device=self.workspace.device)
+        elif (out.dtype != torch.float64 or tuple(out.shape) != (n_phix, ny) or
+              not out.is_contiguous()):
+            raise ValueError("out must be a contiguous float64 tensor of shape (n_phix, N_y)")
+        bte_reconstruct(self.handle, n_phix, out.data_ptr())
         return out
 
     def set_tuning(self, kernel=None, rows_per_wave=None, waves_per_block=None, graph_steps=None):

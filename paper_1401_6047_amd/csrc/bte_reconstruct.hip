@@ -1,0 +1,226 @@
+// f(phi_x, phi_y) on a uniform phi_x grid from the Fourier state (Sec. 2,
+// Eq. f_fourier):
+//
+//     f[j][m] = sum_{n < N_x} a_n(m) cos(n x_j) + b_n(m) sin(n x_j),
+//     x_j = -pi + 2 pi j / M,  j = 0 .. M-1.
+//
+// This is a dense product F = T Z with T[j][k] the trigonometric matrix and
+// Z[k][m] the coefficients, k = 2n for the cosine/a_n pair and 2n+1 for the
+// sine/b_n pair (K = 2 N_x), so it runs on the FP64 matrix cores
+// (16 x 16 x 4 instructions, FP64 products and sums).  The trigonometric
+// operand is never stored: each lane produces its own entries of T.
+//   - The A operand of an instruction is 16 samples j x 4 values of k; the
+//     lane holding (j, k) carries e^{i n x_j} for its n = 2t + (k >> 1) and
+//     advances it by the rotation e^{2 i x_j} per k step of 4 (4 FP64
+//     operations on the vector unit, overlapping the matrix instructions),
+//     reseeded exactly every 64 harmonics from the integer phase
+//     (n j mod M) / M so that the rotation error stays near 64 ulp.
+//   - The B operand (coefficients) is read straight from the state, 16
+//     consecutive phi_y points per row, with the loads P steps ahead.
+//   - A wavefront owns 16 TJ samples x 16 TM points; the four wavefronts of
+//     a block share the points (the coefficient rows reach them through one
+//     L1), and the blocks that share points are placed on the same XCD so
+//     that one L2 holds their rows.
+// Rows of the output are phi_x samples, columns phi_y points (phi_y
+// contiguous, the state's own orientation).
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "bte_internal.h"
+
+namespace bte {
+
+namespace {
+
+using f64x4 = double __attribute__((ext_vector_type(4)));
+
+constexpr int kReconWaves = 4;
+constexpr int kReseedSteps = 32;    // k steps of 4 = 64 harmonics
+constexpr int kXcds = 8;
+
+template <typename T, int TJ, int TM, int P>
+__global__ __launch_bounds__(kReconWaves * 64) void k_reconstruct(const T* __restrict__ a,
+                                                                   const T* __restrict__ b,
+                                                                   int64_t ld, int nx, int ny,
+                                                                   int M, int gx, int gy,
+                                                                   double* __restrict__ out)
+{
+    // XCD-aware tile order: consecutive block ids go round-robin over the
+    // XCDs, so block id -> (xcd = id mod 8, slot = id / 8) and each XCD takes
+    // a contiguous run of tiles, in which the j tiles of one column tile are
+    // adjacent.
+    const int ntile = gx * gy;
+    const int per_xcd = (ntile + kXcds - 1) / kXcds;
+    const int id = blockIdx.x;
+    const int tile = (id % kXcds) * per_xcd + id / kXcds;
+    if (tile >= ntile) return;
+    const int bx = tile / gy, by = tile % gy;
+
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int r16 = lane & 15;
+    const int q = lane >> 4;                 // k offset inside an instruction
+    const int half = q >> 1;                 // n = 2t + half
+    const bool is_sin = (q & 1) != 0;        // odd k: sine / b_n
+    const int m0 = bx * (16 * TM);
+    const int jw = (by * kReconWaves + wave) * (16 * TJ);
+
+    int jj[TJ];
+    double c[TJ], s[TJ], c2[TJ], s2[TJ];
+#pragma unroll
+    for (int i = 0; i < TJ; ++i) {
+        const int j = jw + 16 * i + r16;
+        jj[i] = j < M ? j : M - 1;           // rows past the end shadow the last sample
+        // rotation by 2 x_j = -2 pi + 2 pi (2 j) / M
+        const int64_t p2 = (2 * static_cast<int64_t>(jj[i])) % M;
+        sincospi(2.0 * static_cast<double>(p2) / static_cast<double>(M), &s2[i], &c2[i]);
+        c[i] = 0.0;
+        s[i] = 0.0;
+    }
+    const T* src = is_sin ? b : a;
+    int64_t col[TM];
+#pragma unroll
+    for (int u = 0; u < TM; ++u) {
+        const int m = m0 + 16 * u + r16;
+        col[u] = m < ny ? m : ny - 1;
+    }
+    // Coefficient of k step t (rows n = 2t + half), with the guards: rows
+    // past N_x and b_0 (not part of the series) give 0 and are not read.
+    auto coef = [&](int t, int u) -> double {
+        const int n = 2 * t + half;
+        if (n >= nx || (is_sin && n == 0)) return 0.0;
+        return static_cast<double>(src[n * ld + col[u]]);
+    };
+
+    f64x4 acc[TJ][TM];
+#pragma unroll
+    for (int i = 0; i < TJ; ++i)
+#pragma unroll
+        for (int u = 0; u < TM; ++u) acc[i][u] = f64x4{0.0, 0.0, 0.0, 0.0};
+
+    auto reseed = [&](int t) {
+        const int n = 2 * t + half;
+#pragma unroll
+        for (int i = 0; i < TJ; ++i) {
+            const int64_t k = (static_cast<int64_t>(n) * jj[i]) % M;
+            double ss, cc;
+            sincospi(2.0 * static_cast<double>(k) / static_cast<double>(M), &ss, &cc);
+            const double sg = (n & 1) ? -1.0 : 1.0;   // n x_j = -n pi + 2 pi n j / M
+            c[i] = sg * cc;
+            s[i] = sg * ss;
+        }
+    };
+    auto mma_rotate = [&](const double (&z)[TM]) {
+#pragma unroll
+        for (int i = 0; i < TJ; ++i) {
+            const double av = is_sin ? s[i] : c[i];
+#pragma unroll
+            for (int u = 0; u < TM; ++u)
+                acc[i][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, z[u], acc[i][u], 0, 0, 0);
+        }
+#pragma unroll
+        for (int i = 0; i < TJ; ++i) {
+            const double cn = fma(c[i], c2[i], -s[i] * s2[i]);
+            const double sn = fma(s[i], c2[i], c[i] * s2[i]);
+            c[i] = cn;
+            s[i] = sn;
+        }
+    };
+
+    // Steps 0 .. P-1 are fetched with guards.  In the main loop every row a
+    // prefetch touches exists (2 (t + P) + 1 < N_x), so its loads go out
+    // unconditionally, P steps ahead, through pointers that advance two rows
+    // per step.  The last steps use what is left in the ring, then load
+    // directly.
+    const int nsteps = (nx + 1) / 2;
+    const int full = nx / 2;                 // steps whose two rows both exist
+    static_assert(kReseedSteps % P == 0, "reseeds fall on ring starts");
+    double zb[P][TM];
+#pragma unroll
+    for (int p = 0; p < P; ++p)
+#pragma unroll
+        for (int u = 0; u < TM; ++u) zb[p][u] = coef(p, u);
+    int64_t idx[TM];
+#pragma unroll
+    for (int u = 0; u < TM; ++u) idx[u] = (2 * P + half) * ld + col[u];
+    const int64_t adv = 2 * ld;
+    int t0 = 0;
+    for (; t0 + 2 * P <= full; t0 += P) {
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            if (p == 0 && t0 % kReseedSteps == 0) reseed(t0);   // t0 is a multiple of P
+            mma_rotate(zb[p]);
+#pragma unroll
+            for (int u = 0; u < TM; ++u) {
+                zb[p][u] = static_cast<double>(src[idx[u]]);
+                idx[u] += adv;
+            }
+        }
+    }
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        const int t = t0 + p;
+        if (t < nsteps) {
+            if (p == 0 && t % kReseedSteps == 0) reseed(t);
+            mma_rotate(zb[p]);
+        }
+    }
+    for (int t = t0 + P; t < nsteps; ++t) {
+        double z[TM];
+#pragma unroll
+        for (int u = 0; u < TM; ++u) z[u] = coef(t, u);
+        if (t % kReseedSteps == 0) reseed(t);
+        mma_rotate(z);
+    }
+
+    // accumulator of lane l: rows (l / 16) + 4 e, e = 0..3, of column l mod 16
+    // (the FP64 16 x 16 x 4 layout)
+#pragma unroll
+    for (int i = 0; i < TJ; ++i) {
+#pragma unroll
+        for (int u = 0; u < TM; ++u) {
+            const int m = m0 + 16 * u + r16;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int j = jw + 16 * i + q + 4 * e;
+                if (j < M && m < ny) out[static_cast<int64_t>(j) * ny + m] = acc[i][u][e];
+            }
+        }
+    }
+}
+
+}  // namespace
+
+template <typename T, int TJ, int TM, int P>
+hipError_t launch_shape(hipStream_t stream, const T* a, const T* b, int64_t ld, int nx, int ny,
+                        int M, double* out)
+{
+    const int gx = (ny + 16 * TM - 1) / (16 * TM);
+    const int gy = (M + kReconWaves * 16 * TJ - 1) / (kReconWaves * 16 * TJ);
+    const int64_t ntile = static_cast<int64_t>(gx) * gy;
+    if (ntile > (int64_t{1} << 30)) return hipErrorInvalidValue;
+    const int per_xcd = static_cast<int>((ntile + kXcds - 1) / kXcds);
+    k_reconstruct<T, TJ, TM, P><<<per_xcd * kXcds, kReconWaves * 64, 0, stream>>>(
+        a, b, ld, nx, ny, M, gx, gy, out);
+    return hipGetLastError();
+}
+
+// Tile shapes by measurement at 512 harmonics x 8193 points: one 16-sample
+// row of instructions per wavefront (more rows cost occupancy); 32 points
+// with loads 8 steps ahead up to ~768 samples (43.6 TFLOP/s at 512), 64
+// points 4 steps ahead beyond (50.1 TFLOP/s at 1024).
+template <typename T>
+hipError_t launch_reconstruct(hipStream_t stream, const T* a, const T* b, int64_t ld, int nx,
+                              int ny, int M, double* out)
+{
+    if (M >= 768) return launch_shape<T, 1, 4, 4>(stream, a, b, ld, nx, ny, M, out);
+    return launch_shape<T, 1, 2, 8>(stream, a, b, ld, nx, ny, M, out);
+}
+
+template hipError_t launch_reconstruct<float>(hipStream_t, const float*, const float*, int64_t,
+                                              int, int, int, double*);
+template hipError_t launch_reconstruct<double>(hipStream_t, const double*, const double*, int64_t,
+                                               int, int, int, double*);
+
+}  // namespace bte

@@ -14,6 +14,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdarg>
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -672,6 +673,41 @@ bte_status bte_get_tuning(const bte_solver* s, bte_tuning* t)
 {
     if (!s || !t) return fail(BTE_EINVAL, "solver and tuning must not be NULL");
     *t = s->tune;
+    return BTE_OK;
+}
+
+bte_status bte_reconstruct(bte_solver* s, int32_t n_phix, double* out)
+{
+    if (!s || !out) return fail(BTE_EINVAL, "solver and out must not be NULL");
+    if (reinterpret_cast<uintptr_t>(out) % alignof(double) != 0)
+        return fail(BTE_EINVAL, "out must be 8-byte aligned");
+    if (n_phix < 1 || n_phix > (1 << 20)) return fail(BTE_EINVAL, "n_phix must be in 1..2^20");
+    const hipError_t e =
+        s->fp32() ? bte::launch_reconstruct<float>(s->stream, s->plane<float>(s->cur, 0),
+                                                   s->plane<float>(s->cur, 1), s->L.ld,
+                                                   s->grid.n_x, s->grid.n_y, n_phix, out)
+                  : bte::launch_reconstruct<double>(s->stream, s->plane<double>(s->cur, 0),
+                                                    s->plane<double>(s->cur, 1), s->L.ld,
+                                                    s->grid.n_x, s->grid.n_y, n_phix, out);
+    if (e != hipSuccess) return fail(BTE_EDEVICE, "reconstruct launch: %s", hipGetErrorString(e));
+    return BTE_OK;
+}
+
+bte_status bte_reconstruct_coeffs(const double* a, const double* b, int32_t n_x, int32_t n_y,
+                                  int64_t ld, int32_t n_phix, double* out, void* hip_stream)
+{
+    if (!a || !b || !out) return fail(BTE_EINVAL, "a, b and out must not be NULL");
+    const auto misaligned = [](const void* p) {
+        return reinterpret_cast<uintptr_t>(p) % alignof(double) != 0;
+    };
+    if (misaligned(a) || misaligned(b) || misaligned(out))
+        return fail(BTE_EINVAL, "a, b and out must be 8-byte aligned");
+    if (n_x < 1 || n_y < 1 || ld < n_y) return fail(BTE_EINVAL, "need n_x >= 1, n_y >= 1, ld >= n_y");
+    if (n_x > 16384 || n_y > (1 << 24)) return fail(BTE_EINVAL, "sizes too large");
+    if (n_phix < 1 || n_phix > (1 << 20)) return fail(BTE_EINVAL, "n_phix must be in 1..2^20");
+    const hipError_t e = bte::launch_reconstruct<double>(static_cast<hipStream_t>(hip_stream), a, b,
+                                                         ld, n_x, n_y, n_phix, out);
+    if (e != hipSuccess) return fail(BTE_EDEVICE, "reconstruct launch: %s", hipGetErrorString(e));
     return BTE_OK;
 }
 

@@ -107,6 +107,17 @@ def random_params(seed: int, *, nx: int, ny: int, phi: float = 6.0, dt: float = 
                     mu=float(g.choice(mu_choices)), dt=dt)
 
 
+def random_coeffs(seed: int, nx: int, ny: int, decay: float = 0.0):
+    """Seeded dense coefficient arrays (a, b) of shape [nx, ny], standard
+    normal times exp(-decay * n) in row n; row b[0] is 0."""
+    g = rng(seed)
+    w = np.exp(-decay * np.arange(nx))[:, None]
+    a = g.standard_normal((nx, ny)) * w
+    b = g.standard_normal((nx, ny)) * w
+    b[0] = 0.0
+    return a, b
+
+
 def smooth_state(seed: int, nx: int, ny: int, *, phi: float = 6.0, width: float = 1.5,
                  n_modes: int = 4, amp: float = 0.05):
     """Seeded smooth (a, b) arrays of shape [nx, ny]: a few low harmonics with a

@@ -134,3 +134,22 @@ def test_mlp_library_exports_and_host_validation():
         mlp.bte_mlp_create(0, 0, 256, 1 << 30, 0)
     with pytest.raises(bte.BteError, match="handle"):
         mlp.bte_mlp_forward(0, None, 4, None)
+
+
+def test_reconstruct_host_validation():
+    """Argument checks of the reconstruction entry points run before any
+    device work (NULL pointers, sizes, alignment)."""
+    from paper_1401_6047_amd import bte
+    with pytest.raises(bte.BteError) as ei:
+        bte.bte_reconstruct(0, 16, 4096)
+    assert ei.value.status == bte.BTE_EINVAL
+    for args, needle in (((0, 8, 4, 8, 8, 3, 8, 0), "NULL"),
+                         ((8, 8, 4, 8, 8, 3, 0, 0), "NULL"),
+                         ((8, 12, 4, 8, 8, 3, 8, 0), "aligned"),
+                         ((8, 8, 4, 8, 7, 3, 8, 0), "ld >= n_y"),
+                         ((8, 8, 0, 8, 8, 3, 8, 0), "n_x >= 1"),
+                         ((8, 8, 4, 8, 8, 0, 8, 0), "n_phix"),
+                         ((8, 8, 4, 8, 8, (1 << 20) + 1, 8, 0), "n_phix")):
+        with pytest.raises(bte.BteError) as ei:
+            bte.bte_reconstruct_coeffs(*args)
+        assert ei.value.status == bte.BTE_EINVAL and needle in str(ei.value), (args, str(ei.value))

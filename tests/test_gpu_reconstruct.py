@@ -1,0 +1,131 @@
+"""Parity of f(phi_x, phi_y) reconstruction (Eq. f_fourier) with the oracle's
+direct sum (GPU tests, through the C ABI).
+
+Tolerance: both sides sum N_x terms in FP64; the oracle rounds each angle
+n x_j (up to ~1e-16 * n pi absolute) and the kernel carries its angles by
+rotation, reseeded every 64 harmonics (~64 ulp).  Per element the bound is
+1e-12 * sum_n (|a_n| + |b_n|) of that column.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1401_6047_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1401_6047_amd import bte
+    return bte, torch
+
+
+def bound(a, b):
+    return 1e-12 * (np.abs(a).sum(axis=0) + np.abs(b[1:]).sum(axis=0))[None, :]
+
+
+SHAPES = [(1, 1), (2, 5), (7, 13), (33, 130), (64, 64), (128, 1001), (200, 9)]
+PHIX = [1, 3, 64, 100, 257, 1000]
+
+
+@pytest.mark.parametrize("nx,ny", SHAPES)
+@pytest.mark.parametrize("M", PHIX)
+def test_coeffs_match_oracle(env, nx, ny, M):
+    """Ragged column tiles (8 per wave), partial phi_x blocks (256 per block),
+    M < 2 N_x (aliasing) and M = 1, and a padded row stride."""
+    bte, torch = env
+    a, b = W.random_coeffs(nx * 1009 + ny * 31 + M, nx, ny)
+    ld = ny + 5
+    buf = torch.zeros((2, nx, ld), dtype=torch.float64, device="cuda")
+    buf[0, :, :ny] = torch.from_numpy(a)
+    buf[1, :, :ny] = torch.from_numpy(b)
+    buf[1, 0, :] = float("nan")          # row 0 of b must not be read
+    out = bte.reconstruct(buf[0, :, :ny], buf[1, :, :ny], M)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    ref = oracle.reconstruct(a, b, M)
+    assert got.shape == (M, ny)
+    err = np.abs(got - ref)
+    assert np.all(err <= bound(a, b)), f"max err {err.max():.3e}"
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_solver_state(env, precision):
+    """bte_reconstruct reads the solver's whole grid (FP32-bulk state widened)."""
+    bte, torch = env
+    w = W.random_params(77, nx=40, ny=301, phi=6.0, dt=2e-3)
+    a, b = W.random_coeffs(78, w.nx, w.ny, decay=0.05)
+    s = bte.Solver.from_workload(w, precision=precision)
+    s.set_state(a, b)
+    f = s.reconstruct(130).cpu().numpy()
+    s.close()
+    if precision == 1:      # the state is stored in FP32 (rounded to nearest on the way in)
+        a = a.astype(np.float32).astype(np.float64)
+        b = b.astype(np.float32).astype(np.float64)
+    ref = oracle.reconstruct(a, b, 130)
+    assert np.all(np.abs(f - ref) <= bound(a, b))
+
+
+def test_equilibrium_at_full_size(env):
+    """512 x 8193 (the large low-temperature workload) at step 0, 512 phi_x
+    samples, the launch the benchmark times: 4000 sampled elements against
+    the oracle's sum over the oracle's own equilibrium coefficients, and the
+    discrete normalisation sqrt(alpha) (2 pi / M) dphi sum f = 1."""
+    bte, torch = env
+    w = W.LARGE
+    s = bte.Solver.from_workload(w)
+    f = s.reconstruct(512)
+    torch.cuda.synchronize()
+    s.close()
+    pb = oracle.Problem(nx=w.nx, ny=w.ny, phiy_min=w.phiy_min, phiy_max=w.phiy_max,
+                        E_dc=w.E_dc, E_w=w.E_w, omega=w.omega, B=w.B, mu=w.mu, dt=w.dt,
+                        alpha=w.alpha)
+    a0 = oracle.equilibrium(pb)
+    g = W.rng(512)
+    rows = g.integers(0, 512, 4000)
+    cols = g.integers(0, w.ny, 4000)
+    ref = oracle.reconstruct(a0, np.zeros_like(a0), 512, cols=cols, rows=rows)
+    got = f[torch.as_tensor(rows, device="cuda"), torch.as_tensor(cols, device="cuda")].cpu().numpy()
+    tol = 1e-12 * np.abs(a0[:, cols]).sum(axis=0)
+    assert np.all(np.abs(got - ref) <= tol)
+    dphi = (w.phiy_max - w.phiy_min) / (w.ny - 1)
+    norm = np.sqrt(w.alpha) * (2 * np.pi / 512) * dphi * f.sum().item()
+    assert abs(norm - 1.0) < 1e-9
+
+
+def test_random_state_at_full_size(env):
+    """512 x 8193 seeded dense coefficients through bte_set_state, sampled
+    elements against the oracle."""
+    bte, torch = env
+    w = W.LARGE
+    a, b = W.random_coeffs(8193, w.nx, w.ny, decay=0.01)
+    s = bte.Solver.from_workload(w)
+    s.set_state(a, b)
+    f = s.reconstruct(512)
+    torch.cuda.synchronize()
+    s.close()
+    g = W.rng(8194)
+    rows = g.integers(0, 512, 4000)
+    cols = g.integers(0, w.ny, 4000)
+    ref = oracle.reconstruct(a, b, 512, cols=cols, rows=rows)
+    got = f[torch.as_tensor(rows, device="cuda"), torch.as_tensor(cols, device="cuda")].cpu().numpy()
+    tol = 1e-12 * (np.abs(a[:, cols]).sum(axis=0) + np.abs(b[1:, cols]).sum(axis=0))
+    assert np.all(np.abs(got - ref) <= tol)
+
+
+def test_argument_errors(env):
+    bte, torch = env
+    a = torch.zeros((4, 8), dtype=torch.float64, device="cuda")
+    out = torch.empty((3, 8), dtype=torch.float64, device="cuda")
+    st = torch.cuda.current_stream().cuda_stream
+    for args in ((a.data_ptr(), a.data_ptr(), 4, 8, 8, 0, out.data_ptr(), st),
+                 (a.data_ptr(), a.data_ptr(), 4, 8, 7, 3, out.data_ptr(), st),
+                 (a.data_ptr(), 0, 4, 8, 8, 3, out.data_ptr(), st),
+                 (a.data_ptr(), a.data_ptr(), 4, 8, 8, 3, out.data_ptr() + 4, st),
+                 (a.data_ptr(), a.data_ptr(), 0, 8, 8, 3, out.data_ptr(), st)):
+        with pytest.raises(bte.BteError):
+            bte.bte_reconstruct_coeffs(*args)
