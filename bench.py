@@ -73,6 +73,8 @@ def parse():
                     help="of those, how many the plain FP64 solver also runs")
     ap.add_argument("--warm-train", type=int, default=2048,
                     help="coarse-grid training states for the warm-started sweep (0: no warm run)")
+    ap.add_argument("--reconstruct", type=int, default=512,
+                    help="phi_x samples of the timed f(phi_x, phi_y) reconstruction (0: skip)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     return ap.parse_args()
@@ -354,8 +356,8 @@ def main():
                                                       "achieved_GBs", "avg_launch_us", "kernel",
                                                       "tuning")}
                             for k, v in variants.items()}
-    if not args.no_variants:
-        line["reconstruct"] = reconstruct_bench(bte, torch, w)
+    if args.reconstruct > 0:
+        line["reconstruct"] = reconstruct_bench(bte, torch, w, n_phix=args.reconstruct)
     if args.copy_mib > 0:
         # a plain device-to-device copy of known size, for scaling the HBM
         # traffic counters of the step kernel

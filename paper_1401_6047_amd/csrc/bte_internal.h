@@ -124,11 +124,4 @@ template <typename T>
 hipError_t launch_reduce_obs(const Consts& cs, const T* a_h, const T* b_h, const double* acc_v,
                              const double* acc_vc, double* out, hipStream_t st);
 
-// out[j * ny + m] = sum_{n < nx} a[n][m] cos(n x_j) + b[n][m] sin(n x_j),
-// x_j = -pi + 2 pi j / M (bte_reconstruct.hip); row stride ld elements,
-// row 0 of b not read.
-template <typename T>
-hipError_t launch_reconstruct(hipStream_t stream, const T* a, const T* b, int64_t ld, int nx,
-                              int ny, int M, double* out);
-
 }  // namespace bte

@@ -27,7 +27,7 @@
 
 #include <cstdint>
 
-#include "bte_internal.h"
+#include "bte_reconstruct.h"
 
 namespace bte {
 

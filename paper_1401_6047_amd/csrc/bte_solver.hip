@@ -22,6 +22,7 @@
 
 #include "../../include/bte.h"
 #include "bte_internal.h"
+#include "bte_reconstruct.h"
 
 namespace {
 thread_local std::string g_last_error;
