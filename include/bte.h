@@ -249,11 +249,28 @@ typedef struct {
     int32_t reserved;       /* must be 0 */
 } bte_batch_config;
 
+/* How a batch is laid out on the GPU. */
+typedef enum {
+    /* One persistent launch; each workgroup takes the next instance from a
+       device work queue and runs it to convergence.  Device memory: one state
+       slot per workgroup.  A batch of few long instances runs at one
+       workgroup per instance. */
+    BTE_BATCH_PERSISTENT = 0,
+    /* Every instance has its own state slot; each pass is one launch over the
+       tiles of all instances still running (one or two steps each), followed
+       by a bookkeeping launch that closes periods and sizes the next pass.
+       The host replays captured groups of passes until no instance is left.
+       Same per-cell arithmetic, step sequence and reductions as the
+       persistent schedule: identical results. */
+    BTE_BATCH_WIDE = 1
+} bte_batch_schedule;
+
 typedef struct {
     int32_t kernel;         /* BTE_KERNEL_FUSED or BTE_KERNEL_FUSED2 */
     int32_t rows_per_wave;  /* 1 .. 62 (58 for FUSED2) */
     int32_t waves_per_group;/* wavefronts per workgroup: 2, 4 or 8 */
     int32_t groups;         /* persistent workgroups (0: fill the GPU) */
+    int32_t schedule;       /* a bte_batch_schedule */
 } bte_batch_tuning;
 
 typedef struct {
@@ -273,8 +290,11 @@ typedef struct {
 
 typedef struct bte_batch bte_batch;
 
-/* Device bytes for a batch (instance tables, per-workgroup state slots sized
-   for the largest n_y, results), for the given tuning (NULL: default). */
+/* Device bytes for a batch (instance tables, state slots sized for the
+   largest n_y -- one per workgroup, or one per instance for the wide
+   schedule --, results), for the given tuning.  NULL tuning: FUSED2, 25
+   harmonics per wave, 8 wavefronts per group, and the wide schedule unless
+   its slots would take more than 64 GiB (then the persistent one). */
 bte_status bte_batch_workspace_bytes(const bte_batch_config* cfg, int32_t n,
                                      const bte_instance* inst, const bte_batch_tuning* tuning,
                                      size_t* bytes);
@@ -300,8 +320,20 @@ bte_status bte_batch_set_warm_start(bte_batch* b, const float* dev_coeffs);
    (phase 0 of the field), in the warm-start encoding above.  NULL: none. */
 bte_status bte_batch_set_state_output(bte_batch* b, float* dev_coeffs);
 
-/* Queue the sweep (one graph launch); returns immediately. */
+/* Run the sweep.  Persistent schedule: queue it (one graph launch) and
+   return immediately.  Wide schedule: set up, then replay groups of passes
+   until every instance has stopped, synchronising the stream after each group;
+   returns when the sweep is done (bte_batch_advance does the same in slices). */
 bte_status bte_batch_run(bte_batch* b);
+
+/* Wide schedule only: advance the sweep by at most `max_replays` >= 1 groups
+   of passes (64 passes each), starting it first (set-up from the equilibrium
+   or the warm start) when no sweep is in progress.  Synchronises the stream
+   after each group and writes the number of instances still running to
+   *remaining (host pointer); 0 means the sweep is done and its results are
+   readable.  BTE_ESTATE for the persistent schedule; BTE_EDEVICE if the
+   sweep exceeds the pass count that max_periods allows (it cannot). */
+bte_status bte_batch_advance(bte_batch* b, int32_t max_replays, int32_t* remaining);
 
 /* Wait for the sweep and copy the n results out (synchronises). */
 bte_status bte_batch_results(bte_batch* b, bte_result* out);

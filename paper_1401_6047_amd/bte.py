@@ -21,6 +21,7 @@ HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "bte.h")
 BTE_OK, BTE_EINVAL, BTE_ENOMEM, BTE_EDEVICE, BTE_EUNSTABLE, BTE_ESTATE = 0, -1, -2, -3, -4, -5
 BTE_FP64, BTE_FP32_BULK = 0, 1
 BTE_KERNEL_FUSED, BTE_KERNEL_TWO_PASS, BTE_KERNEL_FUSED2, BTE_KERNEL_FUSED3 = 0, 1, 2, 3
+BTE_BATCH_PERSISTENT, BTE_BATCH_WIDE = 0, 1
 STATUS_NAMES = {0: "BTE_OK", -1: "BTE_EINVAL", -2: "BTE_ENOMEM", -3: "BTE_EDEVICE",
                 -4: "BTE_EUNSTABLE", -5: "BTE_ESTATE"}
 
@@ -71,7 +72,8 @@ class bte_batch_config(ctypes.Structure):
 
 class bte_batch_tuning(ctypes.Structure):
     _fields_ = [("kernel", ctypes.c_int32), ("rows_per_wave", ctypes.c_int32),
-                ("waves_per_group", ctypes.c_int32), ("groups", ctypes.c_int32)]
+                ("waves_per_group", ctypes.c_int32), ("groups", ctypes.c_int32),
+                ("schedule", ctypes.c_int32)]
 
 
 class bte_result(ctypes.Structure):
@@ -120,6 +122,7 @@ def _load():
         "bte_batch_set_warm_start": ([vp, vp], ctypes.c_int),
         "bte_batch_set_state_output": ([vp, vp], ctypes.c_int),
         "bte_batch_run": ([vp], ctypes.c_int),
+        "bte_batch_advance": ([vp, ctypes.c_int32, P(ctypes.c_int32)], ctypes.c_int),
         "bte_batch_results": ([vp, P(bte_result)], ctypes.c_int),
         "bte_batch_get_tuning": ([vp, P(bte_batch_tuning)], ctypes.c_int),
         "bte_batch_destroy": ([vp], None),
@@ -297,6 +300,13 @@ def bte_batch_set_state_output(h: int, dev_ptr: int):
 
 def bte_batch_run(h: int):
     _check(_lib.bte_batch_run(ctypes.c_void_p(h)), "bte_batch_run")
+
+
+def bte_batch_advance(h: int, max_replays: int) -> int:
+    left = ctypes.c_int32(0)
+    _check(_lib.bte_batch_advance(ctypes.c_void_p(h), int(max_replays), ctypes.byref(left)),
+           "bte_batch_advance")
+    return int(left.value)
 
 
 def bte_batch_results(h: int, n: int):
@@ -480,15 +490,22 @@ class Batch:
     largest instance's grid (one- and two-step kernel forms only)."""
 
     def __init__(self, cfg: bte_batch_config, instances, tuning=None, waves_per_group=8,
-                 groups=0, device="cuda", stream=None, autotune=True):
+                 groups=0, device="cuda", stream=None, autotune=True, schedule=None):
         import torch
         self.cfg = cfg
         self.instances = list(instances)
         self.n = len(self.instances)
         self.stream = stream if stream is not None else torch.cuda.current_stream(device)
         self.tune_us = None
+        if schedule is None:
+            # wide (one state slot per instance) unless the slots would pass
+            # 64 GiB, the library's own default rule
+            ny = max(w.ny for w in self.instances)
+            elem = 4 if cfg.precision == BTE_FP32_BULK else 8
+            slot = 8 * (cfg.n_x + 8) * (ny + 128) * elem
+            schedule = BTE_BATCH_WIDE if slot * self.n <= 64 * 2 ** 30 else BTE_BATCH_PERSISTENT
         if tuning is None:
-            tuning = bte_batch_tuning(BTE_KERNEL_FUSED2, 25, waves_per_group, groups)
+            tuning = bte_batch_tuning(BTE_KERNEL_FUSED2, 25, waves_per_group, groups, schedule)
             if autotune:
                 big = max(self.instances, key=lambda w: w.ny)
                 g = make_grid(cfg.n_x, big.ny, cfg.phiy_min, cfg.phiy_max)
@@ -543,6 +560,19 @@ class Batch:
         import time
         import torch
         t0 = time.perf_counter()
+        if self.tuning.schedule == BTE_BATCH_WIDE:
+            # the host drives the passes; advance in slices so that progress
+            # can be reported
+            last = t0
+            left = bte_batch_advance(self.handle, 1)
+            while left > 0:
+                left = bte_batch_advance(self.handle, 16)
+                now = time.perf_counter()
+                if left and log and now - last >= report_every:
+                    log(f"  batch of {self.n} instances: {left} running, {now - t0:.0f} s",
+                        flush=True)
+                    last = now
+            return time.perf_counter() - t0
         done = torch.cuda.Event()
         bte_batch_run(self.handle)
         done.record(self.stream)

@@ -33,13 +33,13 @@ from . import workloads as W
 
 
 def sweep_states(instances, nx, phiy, dt, precision=bte.BTE_FP32_BULK, tol=1e-6,
-                 max_periods=400, log=None, confirm=1):
+                 max_periods=400, log=None, confirm=1, schedule=None):
     """Run a batched sweep to convergence; return (results, states (n,64,128)
     CUDA tensor, wall seconds)."""
     import torch
     cfg = bte.make_batch_config(nx, -phiy, phiy, dt, precision=precision, tol=tol,
                                 min_periods=2, max_periods=max_periods, confirm=confirm)
-    b = bte.Batch(cfg, instances)
+    b = bte.Batch(cfg, instances, schedule=schedule)
     out = torch.zeros((len(instances), 64, 128), dtype=torch.float32, device="cuda")
     b.set_state_output(out)
     secs = b.run(log=log)
@@ -49,11 +49,11 @@ def sweep_states(instances, nx, phiy, dt, precision=bte.BTE_FP32_BULK, tol=1e-6,
 
 
 def sweep(instances, nx, phiy, dt, warm=None, precision=bte.BTE_FP32_BULK, tol=1e-6,
-          max_periods=400, log=None, confirm=1):
+          max_periods=400, log=None, confirm=1, schedule=None):
     """Run a batched sweep (cold, or warm from coefficients); (results, seconds)."""
     cfg = bte.make_batch_config(nx, -phiy, phiy, dt, precision=precision, tol=tol,
                                 min_periods=2, max_periods=max_periods, confirm=confirm)
-    b = bte.Batch(cfg, instances)
+    b = bte.Batch(cfg, instances, schedule=schedule)
     b.set_warm_start(warm)
     secs = b.run(log=log)
     res = b.results()

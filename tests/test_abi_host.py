@@ -110,6 +110,16 @@ def test_batch_workspace_bytes_and_validation():
     bad = bte.bte_batch_tuning(bte.BTE_KERNEL_TWO_PASS, 8, 8, 0)   # not a batch kernel form
     with pytest.raises(bte.BteError):
         bte.bte_batch_workspace_bytes(_cfg(), [_W()], bad)
+    bad = bte.bte_batch_tuning(bte.BTE_KERNEL_FUSED2, 8, 8, 0, 2)    # unknown schedule
+    with pytest.raises(bte.BteError) as ei:
+        bte.bte_batch_workspace_bytes(_cfg(), [_W()], bad)
+    assert ei.value.status == bte.BTE_EINVAL and "schedule" in str(ei.value)
+    # the wide schedule holds one state slot per instance, the persistent one
+    # per workgroup
+    inst = [_W(ny=401)] * 4
+    t = bte.bte_batch_tuning(bte.BTE_KERNEL_FUSED2, 25, 8, 16, bte.BTE_BATCH_PERSISTENT)
+    w = bte.bte_batch_tuning(bte.BTE_KERNEL_FUSED2, 25, 8, 16, bte.BTE_BATCH_WIDE)
+    assert bte.bte_batch_workspace_bytes(_cfg(), inst, w) < bte.bte_batch_workspace_bytes(_cfg(), inst, t)
 
 
 def test_mlp_library_exports_and_host_validation():

@@ -1,6 +1,7 @@
-"""Batched sweep (one persistent launch, work queue, per-period convergence)
-against the FP64 oracle run period by period, and against itself across
-launch shapes, precision and warm starts."""
+"""Batched sweep (persistent schedule: one launch with a work queue; wide
+schedule: one launch per pass over all running instances) with per-period
+convergence, against the FP64 oracle run period by period, and against itself
+across schedules, launch shapes, precision and warm starts."""
 import math
 
 import numpy as np
@@ -189,3 +190,67 @@ def test_batch_confirm_requires_consecutive_small_changes(bte, small, small_ref)
         assert r["converged"] == 1 and r["periods"] == want, (w.name, r, want)
         A, v, pend = ref[want - 1]
         assert relerr(r["absorption"], A, 1e-2 * w.E_w) < 1e-10
+
+
+def test_wide_schedule_matches_persistent_bitwise(bte, small, small_ref):
+    """The wide schedule (one launch per pass over all running instances, one
+    state slot per instance) runs the same steps, sums and stopping rule:
+    identical results in FP64 and FP32 bulk, across tile shapes, with warm
+    starts and state export; and against the oracle per period."""
+    import torch
+    F1, F2, WIDE = bte.BTE_KERNEL_FUSED, bte.BTE_KERNEL_FUSED2, bte.BTE_BATCH_WIDE
+    # (FP32 bulk rounds the stored state once per pass, so the one- and
+    # two-step forms differ there; each wide run is compared with the
+    # persistent run of the same form)
+    for precision in (0, bte.BTE_FP32_BULK):
+        for kernel, R, wpg in ((F2, 25, 8), (F1, 7, 4), (F2, 58, 2)):
+            ref = run_batch(bte, small, precision=precision,
+                            tuning=bte.bte_batch_tuning(kernel, 25, 8, 0))
+            res = run_batch(bte, small, precision=precision,
+                            tuning=bte.bte_batch_tuning(kernel, R, wpg, 0, WIDE))
+            for a, b in zip(ref, res):
+                assert a == b, (precision, kernel, R, wpg, a, b)
+    res = run_batch(bte, small, tuning=bte.bte_batch_tuning(F2, 25, 4, 0, WIDE))
+    for w, r, ref in zip(small, res, small_ref):
+        A, v, pend = ref[r["periods"] - 1]
+        assert r["steps"] == pend and r["converged"] == 1
+        assert relerr(r["absorption"], A, 1e-2 * w.E_w) < 1e-10
+    # warm start and state export, twice in a row on one handle
+    outs = []
+    for schedule in (0, WIDE):
+        b = make_batch(bte, small, tuning=bte.bte_batch_tuning(F2, 25, 8, 0, schedule))
+        out = torch.zeros((len(small), 64, 128), dtype=torch.float32, device="cuda")
+        b.set_state_output(out)
+        b.run(log=None)
+        first = b.results()
+        warm = out.clone()
+        b.set_warm_start(warm)
+        b.run(log=None)
+        second = b.results()
+        b.close()
+        outs.append((first, second, out.cpu().numpy(), warm.cpu().numpy()))
+    (f0, s0, o0, w0), (f1, s1, o1, w1) = outs
+    assert f0 == f1 and s0 == s1
+    np.testing.assert_array_equal(o0, o1)
+    np.testing.assert_array_equal(w0, w1)
+    assert sum(r["periods"] for r in s1) < sum(r["periods"] for r in f1)
+
+
+def test_wide_schedule_advance_in_slices(bte, small):
+    """bte_batch_advance drives the same sweep in slices; the persistent
+    schedule refuses it."""
+    F2, WIDE = bte.BTE_KERNEL_FUSED2, bte.BTE_BATCH_WIDE
+    ref = run_batch(bte, small, tuning=bte.bte_batch_tuning(F2, 25, 8, 0, WIDE))
+    b = make_batch(bte, small, tuning=bte.bte_batch_tuning(F2, 25, 8, 0, WIDE))
+    left, calls = len(small), 0
+    while left:
+        left = bte.bte_batch_advance(b.handle, 1)
+        calls += 1
+        assert 0 <= left <= len(small)
+    assert calls > 1 and b.results() == ref
+    b.close()
+    p = make_batch(bte, small, tuning=bte.bte_batch_tuning(F2, 25, 8, 0))
+    with pytest.raises(bte.BteError) as ei:
+        bte.bte_batch_advance(p.handle, 1)
+    assert ei.value.status == bte.BTE_ESTATE
+    p.close()
