@@ -292,8 +292,8 @@ typedef struct bte_batch bte_batch;
 
 /* Device bytes for a batch (instance tables, state slots sized for the
    largest n_y -- one per workgroup, or one per instance for the wide
-   schedule --, results), for the given tuning.  NULL tuning: FUSED2, 25
-   harmonics per wave, 8 wavefronts per group, and the wide schedule unless
+   schedule --, results), for the given tuning.  NULL tuning: FUSED2, 58
+   harmonics per wave, 4 wavefronts per group, and the wide schedule unless
    its slots would take more than 64 GiB (then the persistent one). */
 bte_status bte_batch_workspace_bytes(const bte_batch_config* cfg, int32_t n,
                                      const bte_instance* inst, const bte_batch_tuning* tuning,

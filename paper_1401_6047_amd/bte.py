@@ -486,11 +486,15 @@ class Batch:
     """A batched sweep of independent instances (see bte_batch_* in bte.h).
 
     `instances` are objects with E_dc, E_w, omega, B, mu, ny (e.g. Workload).
-    With `tuning=None` the tile shape is picked by the autotuner on the
-    largest instance's grid (one- and two-step kernel forms only)."""
+    With `tuning=None`: the two-step kernel, 58 harmonics per wave, 4
+    wavefronts per group, and the wide schedule unless its per-instance slots
+    would pass 64 GiB.  `autotune=True` takes the kernel form and harmonics
+    per wave from the single-instance tuner on the largest instance's grid
+    instead (which tunes for one instance filling the GPU, and so picks
+    shapes that are slower in a batch)."""
 
-    def __init__(self, cfg: bte_batch_config, instances, tuning=None, waves_per_group=8,
-                 groups=0, device="cuda", stream=None, autotune=True, schedule=None):
+    def __init__(self, cfg: bte_batch_config, instances, tuning=None, waves_per_group=4,
+                 groups=0, device="cuda", stream=None, autotune=False, schedule=None):
         import torch
         self.cfg = cfg
         self.instances = list(instances)
@@ -505,7 +509,7 @@ class Batch:
             slot = 8 * (cfg.n_x + 8) * (ny + 128) * elem
             schedule = BTE_BATCH_WIDE if slot * self.n <= 64 * 2 ** 30 else BTE_BATCH_PERSISTENT
         if tuning is None:
-            tuning = bte_batch_tuning(BTE_KERNEL_FUSED2, 25, waves_per_group, groups, schedule)
+            tuning = bte_batch_tuning(BTE_KERNEL_FUSED2, 58, waves_per_group, groups, schedule)
             if autotune:
                 big = max(self.instances, key=lambda w: w.ny)
                 g = make_grid(cfg.n_x, big.ny, cfg.phiy_min, cfg.phiy_max)

@@ -654,12 +654,16 @@ struct BatchLayout {
 // those slots stay below this many bytes.
 constexpr double kWideDefaultBytes = 64.0 * (1u << 30);
 
+// Measured on 192 sweep draws (N_x 128, N_y 401-1601, FP32 bulk, wide):
+// 58 harmonics per wave and 4 wavefronts per group ran 37.4 s; 25 / 4 and
+// 40 / 4 40.7 s; 58 / 8 41.8 s; the 5 harmonics the single-instance tuner
+// picks for the largest grid (it fills the GPU with one instance) 63.6 s.
 bte_batch_tuning default_batch_tuning()
 {
     bte_batch_tuning t{};
     t.kernel = BTE_KERNEL_FUSED2;
-    t.rows_per_wave = 25;
-    t.waves_per_group = 8;
+    t.rows_per_wave = 58;
+    t.waves_per_group = 4;
     t.groups = 0;
     t.schedule = BTE_BATCH_WIDE;
     return t;
