@@ -71,11 +71,8 @@ def parse():
                     help="instances of the batched-sweep measurement (0: skip)")
     ap.add_argument("--sweep-fp64", type=int, default=8,
                     help="of those, how many the plain FP64 solver also runs")
-    # The warm-started leg repeats the sweep (about four more minutes at the
-    # default size, where the longest single instance sets the wall time);
-    # its gain is measured at 2048 instances with the warmstart module.
-    ap.add_argument("--warm-train", type=int, default=0,
-                    help="coarse-grid training states for a warm-started sweep (0: no warm run)")
+    ap.add_argument("--warm-train", type=int, default=2048,
+                    help="coarse-grid training states for the warm-started sweep (0: no warm run)")
     ap.add_argument("--reconstruct", type=int, default=512,
                     help="phi_x samples of the timed f(phi_x, phi_y) reconstruction (0: skip)")
     ap.add_argument("--copy-mib", type=int, default=0,
