@@ -223,11 +223,12 @@ bte_status bte_reconstruct_coeffs(const double* a, const double* b, int32_t n_x,
    length: a window of whole steps misses T by up to half a step, and equal
    windows keep that error the same from period to period instead of
    alternating); its absorption A_p and mean drift velocity follow the Sec. 2
-   definitions over those steps.  One persistent,
-   graph-captured kernel launch runs the whole sweep: each workgroup takes the
-   next instance from a device work queue (largest expected cost first) and
-   advances it to convergence with the same per-cell arithmetic as the
-   single-instance solver. */
+   definitions over those steps.  Two schedules run the same per-cell
+   arithmetic as the single-instance solver (bte_batch_schedule): the wide
+   one (default) advances all running instances together, one launch per pass
+   of one or two steps; the persistent one runs the whole sweep in one
+   graph-captured launch in which each workgroup takes the next instance from
+   a device work queue (largest expected cost first). */
 
 typedef struct {
     double E_dc, E_w, omega, B, mu;   /* as in bte_params; omega > 0 */

@@ -1,7 +1,8 @@
-// Batched parameter sweep: one persistent, graph-captured launch runs many
-// independent instances of the superlattice BTE to per-period convergence.
+// Batched parameter sweep: many independent instances of the superlattice
+// BTE run to per-period convergence, in one of two schedules (the wide one
+// is described above its kernels further down).
 //
-// Each workgroup owns a state slot (two ping-pong sets of the four planes,
+// Persistent schedule: one graph-captured launch; each workgroup owns a state slot (two ping-pong sets of the four planes,
 // sized for the largest N_y of the batch, plus the phi_y envelope and the
 // per-phi_y window sums) and loops: take the next instance from a device work
 // queue, initialise it (equilibrium or warm start, then the start-up
