@@ -254,3 +254,24 @@ def test_wide_schedule_advance_in_slices(bte, small):
         bte.bte_batch_advance(p.handle, 1)
     assert ei.value.status == bte.BTE_ESTATE
     p.close()
+
+
+def test_wide_schedule_period_cap_and_repeat_runs(bte, small):
+    """An unreachable tolerance stops every instance at max_periods without
+    convergence, in both schedules alike; a wide handle run twice gives the
+    same results."""
+    F2, WIDE = bte.BTE_KERNEL_FUSED2, bte.BTE_BATCH_WIDE
+    res = {}
+    for schedule in (bte.BTE_BATCH_PERSISTENT, WIDE):
+        b = make_batch(bte, small, tol=1e-300, max_periods=3,
+                       tuning=bte.bte_batch_tuning(F2, 58, 4, 0, schedule))
+        b.run(log=None)
+        first = b.results()
+        b.run(log=None)
+        assert b.results() == first
+        b.close()
+        res[schedule] = first
+    assert res[WIDE] == res[bte.BTE_BATCH_PERSISTENT]
+    for w, r in zip(small, res[WIDE]):
+        L = int(np.rint(2.0 * math.pi / (w.omega * w.dt)))
+        assert r["converged"] == 0 and r["periods"] == 3 and r["steps"] == 3 * L
