@@ -163,3 +163,13 @@ def test_reconstruct_host_validation():
         with pytest.raises(bte.BteError) as ei:
             bte.bte_reconstruct_coeffs(*args)
         assert ei.value.status == bte.BTE_EINVAL and needle in str(ei.value), (args, str(ei.value))
+
+
+def test_batch_advance_host_validation():
+    """bte_batch_advance rejects a NULL batch before any device work."""
+    import ctypes
+    left = ctypes.c_int32(0)
+    rc = bte.lib().bte_batch_advance(None, 1, ctypes.byref(left))
+    assert rc == bte.BTE_EINVAL
+    rc = bte.lib().bte_batch_advance(None, 1, None)
+    assert rc == bte.BTE_EINVAL
