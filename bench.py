@@ -218,7 +218,7 @@ def cpu_baseline(w, sample_steps):
 def sweep_bench(bte, torch, n, n_fp64, n_train, log):
     """Instances per hour of the parameter sweep: the plain FP64 solver (one
     instance at a time, per-period host check) on the first n_fp64 draws, the
-    batched FP32-bulk sweep (one graph-captured persistent launch) on all n,
+    batched FP32-bulk sweep (the library's default schedule: wide) on all n,
     cold and warm-started from the trained network.  Every run stops once
     |A_p - A_{p-1}| < 1e-6 holds for two consecutive periods (a single test
     can stop on a rotating transient); the absorption of the batched runs is
