@@ -7,9 +7,11 @@ imports the product package.
 
 The arithmetic lives in ``bte_oracle.c`` (plain C, FP64, OpenMP over phi_y)
 and ``characteristics.c`` (the same physics by characteristic curves, Sec. 4);
-this module only marshals numpy arrays into them, apart from the quadrature
-nodes of the equilibrium average below.  ``build()`` compiles it with
-gcc.  See the header of ``bte_oracle.c`` for what is computed and which
+this module marshals numpy arrays into them.  Written here in numpy are
+only the quadrature nodes of the equilibrium average, the absorption taken
+period by period from the C oracle's drift-velocity trace, and the B = 0
+continuum references (the Jacobi-Anger periodic state and Tucker's sum).
+``build()`` compiles the C part with gcc.  See the header of ``bte_oracle.c`` for what is computed and which
 passages of the paper each part follows.
 """
 from __future__ import annotations
@@ -269,3 +271,120 @@ def reconstruct(a: np.ndarray, b: np.ndarray, n_phix: int,
     x = -np.pi + 2.0 * np.pi * np.arange(n_phix) / n_phix
     ang = np.outer(x, n)
     return np.cos(ang) @ a + np.sin(ang) @ b
+
+
+# ---------------------------------------------------------------------------
+# Absorption period by period (Sec. 2 absorption, taken over each ac period).
+# ---------------------------------------------------------------------------
+def period_steps(omega: float, dt: float) -> int:
+    """Whole steps per ac period: L = round(2 pi / (omega dt))."""
+    return max(1, int(np.rint(2.0 * np.pi / (omega * dt))))
+
+
+@dataclass
+class Period:
+    absorption: float   # A_p: (2 I_0/I_1) mean over the period of (v - <v>_p) cos(omega t)
+    v_avg: float        # <v>_p: mean drift velocity over the period
+    end: int            # last step of the period, p L
+    plain: float        # (2 I_0/I_1) mean of v cos(omega t) over the same steps (no mean taken out)
+
+
+def run_periods(pb: Problem, n_periods: int, *, n_threads: int = 0) -> list[Period]:
+    """The oracle run period by period from f0 (start-up at step 0, phase 0 of
+    the field).  Period p covers the steps (p-1) L < k <= p L, L =
+    period_steps(omega, dt): windows of one length, so that the half-step by
+    which L dt misses 2 pi / omega is the same in every period.  The
+    absorption of a period is the Sec. 2 average of (2 I_0/I_1) v cos(omega t)
+    over its steps with the period's mean drift velocity taken out first: on
+    a window of exactly one period the two agree (the cosine averages to
+    zero); on a window of whole steps the plain average also picks up
+    <v> times the window's cosine mean, a dc leak that alternates in sign
+    from period to period.  t_k = k dt; v_k from the oracle's trace."""
+    L = period_steps(pb.omega, pb.dt)
+    scale = 2.0 / bessel_ratios(pb.mu, 1)[1]
+    out, state, k = [], None, 0
+    for p in range(1, n_periods + 1):
+        r = run(pb, L, state=state, k0=k, trace=True, n_threads=n_threads)
+        steps = np.arange(k + 1, k + L + 1, dtype=np.float64)
+        c = np.cos(pb.omega * (steps * pb.dt))
+        v = r.v_trace
+        vbar = float(np.mean(v))
+        out.append(Period(absorption=scale * float(np.mean((v - vbar) * c)), v_avg=vbar,
+                          end=k + L, plain=scale * float(np.mean(v * c))))
+        state, k = (r.a_h, r.b_h, r.a_f, r.b_f), k + L
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Continuum references at B = 0 (Sec. 2 Fourier system, harmonic 1).
+# ---------------------------------------------------------------------------
+# At B = 0 the transport terms vanish except the field term, so the harmonics
+# decouple.  For harmonic 1, w = a_1 + i b_1 obeys dw/dt = a^(0)_1 - (1 - i
+# E(t)) w at every phi_y, and v_dr = pi sqrt(alpha) \int b_1 dphi_y.  With
+# u = w / a^(0)_1 and the normalisation of a^(0)_1 (its phi_y integral is
+# (I_1/I_0) / (pi sqrt(alpha))), v_dr = (I_1/I_0) Im u, where u solves
+#     du/dt = 1 - (1 - i E(t)) u,   E(t) = E_dc + E_w cos(omega t).
+# Its periodic solution follows from the Jacobi-Anger expansion
+# e^{i a sin(omega t)} = sum_l J_l(a) e^{i l omega t}, a = E_w / omega.
+def continuum_u(E_dc: float, E_w: float, omega: float, t, lmax: int = 30) -> np.ndarray:
+    """Periodic solution u(t) = sum_{n,l} J_n(a) J_l(a) e^{i (n - l) omega t} /
+    (1 - i (E_dc + l omega)) of du/dt = 1 - (1 - i E(t)) u (the harmonic-1
+    amplitude at B = 0 in units of its equilibrium value)."""
+    import scipy.special as sp
+    t = np.asarray(t, dtype=np.float64)
+    a = E_w / omega
+    l = np.arange(-lmax, lmax + 1)
+    J = sp.jv(l, a)
+    coef_l = J / (1.0 - 1j * (E_dc + l * omega))
+    ph_n = np.exp(1j * np.outer(t, l) * omega) @ J              # sum_n J_n e^{i n w t}
+    ph_l = np.exp(-1j * np.outer(t, l) * omega) @ coef_l        # sum_l J_l e^{-i l w t} / (...)
+    return ph_n * ph_l
+
+
+def tucker_absorption(E_dc: float, E_w: float, omega: float, lmax: int = 60) -> float:
+    """Period average of (2 I_0/I_1) v_dr cos(omega t) for the periodic state
+    at B = 0: 2 <Im u cos(omega t)>, which the Jacobi-Anger form above sums to
+    sum_l J_l(a) [J_{l+1}(a) + J_{l-1}(a)] xi(E_dc + l omega), xi(x) = x/(1+x^2),
+    a = E_w/omega (Tucker's closed form as derived from the Fourier system;
+    the paper prints it with an extra factor 2 I_1/I_0)."""
+    import scipy.special as sp
+    a = E_w / omega
+    l = np.arange(-lmax, lmax + 1)
+    x = E_dc + l * omega
+    return float(np.sum(sp.jv(l, a) * (sp.jv(l + 1, a) + sp.jv(l - 1, a)) * x / (1.0 + x * x)))
+
+
+# ---------------------------------------------------------------------------
+# Resolution diagnostics of a whole-grid state.
+# ---------------------------------------------------------------------------
+def edge_width(ny: int) -> int:
+    """phi_y points in each edge strip: max(1, ceil(N_y / 64))."""
+    return max(1, -(-ny // 64))
+
+
+def top_harmonics(nx: int) -> int:
+    """Harmonics counted as the top of the spectrum: max(1, N_x // 8)."""
+    return max(1, nx // 8)
+
+
+def resolution_diagnostics(pb: Problem, a: np.ndarray, b: np.ndarray) -> tuple[float, float]:
+    """(edge_mass, top_harm_mass) of the state (a, b) ([N_x, N_y] arrays).
+
+    edge_mass: the normalisation integral of Sec. 2, 2 pi sqrt(alpha) dphi
+    sum_m a_0(m), taken over |a_0| in the outer edge_width(N_y) points on each
+    side of the phi_y box.  top_harm_mass: the share of the integral of f^2
+    over phi_x in [-pi, pi) and the box carried by the top top_harmonics(N_x)
+    harmonics; by Parseval's theorem for the Fourier series of Sec. 2 that
+    integral is pi dphi sum_m [2 a_0^2 + sum_{n>=1} (a_n^2 + b_n^2)]."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.array(b, dtype=np.float64)
+    b[0] = 0.0
+    dphi = (pb.phiy_max - pb.phiy_min) / (pb.ny - 1)
+    w = edge_width(pb.ny)
+    edge = np.abs(a[0, :w]).sum() + np.abs(a[0, pb.ny - w:]).sum()
+    edge_mass = 2.0 * np.pi * np.sqrt(pb.alpha) * dphi * edge
+    h = top_harmonics(pb.nx)
+    energy = a * a + b * b
+    total = 2.0 * np.sum(a[0] ** 2) + np.sum(energy[1:])
+    top = np.sum(energy[pb.nx - h:])
+    return float(edge_mass), float(top / total) if total > 0 else 0.0

@@ -161,3 +161,83 @@ def decode(coeffs, a0):
     for n in range(1, min(HARM + 1, nx)):
         b[n] = np.interp(pos, samples, c[HARM + n - 1])
     return a, b
+
+
+# --------------------------------------------------------------------------
+# element-wise rounding-error bounds of the network on the GPU
+# --------------------------------------------------------------------------
+# Forward error analysis of the arithmetic the GPU library performs (not of
+# the network's definition above): a product C = A B over K terms whose
+# operands are rounded to a format with unit roundoff u and summed in FP32
+# satisfies, to first order, |fl(C) - C| <= (2u + K u32) |A| |B| element by
+# element, plus |dA| |B| + |A| |dB| from errors already in the operands.
+# GELU is 1.13-Lipschitz (max of Phi(z) + z phi(z)) and its derivative
+# 0.80-Lipschitz (max of |phi(z) (2 - z^2)|), which carries errors through
+# the activations.  The bounds below chain these through the layers in the
+# order of the definition; they are worst-case (every error aligned), so an
+# indexing or data-flow mistake shows up as an excess far above them while
+# correct rounding stays well inside.
+U_BF16 = 2.0 ** -8        # 8 significant bits
+U_F32 = 2.0 ** -24
+GELU_LIP = 1.13
+GELU_GRAD_LIP = 0.80
+
+
+def _prod_bound(A, B, dA, dB, u):
+    K = A.shape[1]
+    aA, aB = np.abs(A), np.abs(B)
+    out = (2.0 * u + K * U_F32) * (aA @ aB)
+    if dA is not None:
+        out = out + dA @ aB
+    if dB is not None:
+        out = out + aA @ dB
+    return out
+
+
+def _layers(theta, norm, features, bf16):
+    p = unpack(theta)
+    f = forward(theta, norm, features)
+    u = U_BF16 if bf16 else U_F32
+    # layer 1 on the vector ALUs in FP32 (5 terms), bias add and GELU in FP32
+    d_xn = 3.0 * U_F32 * np.abs(f["xn"])
+    dZ1 = _prod_bound(f["xn"], p["W1"].T, d_xn, None, U_F32) + U_F32 * np.abs(f["Z1"])
+    dH1 = GELU_LIP * dZ1 + 4.0 * U_F32 * np.abs(f["H1"])
+    dZ2 = _prod_bound(f["H1"], p["W2"].T, dH1, None, u) + U_F32 * np.abs(f["Z2"])
+    dH2 = GELU_LIP * dZ2 + 4.0 * U_F32 * np.abs(f["H2"])
+    dY = _prod_bound(f["H2"], p["W3"].T, dH2, None, u) + U_F32 * np.abs(f["Y"])
+    return p, f, u, {"xn": d_xn, "Z1": dZ1, "H1": dH1, "Z2": dZ2, "H2": dH2, "Y": dY}
+
+
+def predict_error_bound(theta, norm, features, bf16: bool):
+    """Element-wise bound of |GPU predict - predict| (rows x 64 x 128)."""
+    _, f, _, d = _layers(theta, norm, features, bf16)
+    Y = f["Y"] / norm[2]
+    return (d["Y"] / norm[2] + U_F32 * np.abs(Y)).reshape(-1, ROWS, COLS)
+
+
+def loss_grad_error_bound(theta, norm, features, coeffs, bf16: bool):
+    """Element-wise bound of |GPU gradient - gradient| in the flat parameter
+    layout, following the backward pass of loss_grad."""
+    p, f, u, d = _layers(theta, norm, features, bf16)
+    n = f["Y"].shape[0]
+    t = norm[2] * np.asarray(coeffs, dtype=np.float64).reshape(n, N_OUT)
+    R = f["Y"] - t
+    dY = 2.0 * R / (n * N_OUT)
+    e_dY = 2.0 * (d["Y"] + 2.0 * U_F32 * (np.abs(f["Y"]) + np.abs(t))) / (n * N_OUT)
+    g = {"W3": _prod_bound(dY.T, f["H2"], e_dY.T, d["H2"], u),
+         "b3": e_dY.sum(axis=0) + n * U_F32 * np.abs(dY).sum(axis=0)}
+    A2 = dY @ p["W3"]
+    e_A2 = _prod_bound(dY, p["W3"], e_dY, None, u)
+    gz2 = gelu_grad(f["Z2"])
+    dZ2 = A2 * gz2
+    e_dZ2 = e_A2 * np.abs(gz2) + np.abs(A2) * GELU_GRAD_LIP * d["Z2"] + 4.0 * U_F32 * np.abs(dZ2)
+    g["W2"] = _prod_bound(dZ2.T, f["H1"], e_dZ2.T, d["H1"], u)
+    g["b2"] = e_dZ2.sum(axis=0) + n * U_F32 * np.abs(dZ2).sum(axis=0)
+    A1 = dZ2 @ p["W2"]
+    e_A1 = _prod_bound(dZ2, p["W2"], e_dZ2, None, u)
+    gz1 = gelu_grad(f["Z1"])
+    dZ1 = A1 * gz1
+    e_dZ1 = e_A1 * np.abs(gz1) + np.abs(A1) * GELU_GRAD_LIP * d["Z1"] + 4.0 * U_F32 * np.abs(dZ1)
+    g["W1"] = _prod_bound(dZ1.T, f["xn"], e_dZ1.T, d["xn"], U_F32)
+    g["b1"] = e_dZ1.sum(axis=0) + n * U_F32 * np.abs(dZ1).sum(axis=0)
+    return np.concatenate([g[name].ravel() for name, _ in SHAPES])

@@ -6,7 +6,6 @@ import math
 
 import numpy as np
 import pytest
-import scipy.special as sp
 
 import oracle
 from paper_1401_6047_amd import workloads as W
@@ -24,23 +23,12 @@ def bte():
 
 
 def oracle_periods(w, P):
-    """(A_p, v_p) for p = 1..P from the oracle, each period over steps
-    (p-1) L < k <= p L with L = round(T/dt), resuming the oracle's own state.
-    A_p is the period's mean of (v - <v>) cos(w t) times 2 I_0/I_1: the
-    oracle's window average minus the dc part (2 I_0/I_1) <v> <cos(w t)>,
-    whose cosine mean over the window's steps is summed here directly."""
+    """(A_p, v_p, p L) for p = 1..P from the oracle's period-by-period run
+    (the Sec. 2 absorption of each period with its mean drift velocity taken
+    out, periods of L = round(T/dt) steps)."""
     pb = oracle.Problem(nx=w.nx, ny=w.ny, phiy_min=w.phiy_min, phiy_max=w.phiy_max, E_dc=w.E_dc,
                         E_w=w.E_w, omega=w.omega, B=w.B, mu=w.mu, dt=w.dt)
-    L = int(np.rint(2.0 * math.pi / (w.omega * w.dt)))
-    two_over_ratio = 2.0 * sp.ive(0, w.mu) / sp.ive(1, w.mu)
-    state, k, out = None, 0, []
-    for p in range(1, P + 1):
-        pend = p * L
-        r = oracle.run(pb, pend - k, window=(k, pend), state=state, k0=k)
-        c_mean = np.mean(np.cos(w.omega * (np.arange(k + 1, pend + 1) * w.dt)))
-        out.append((r.absorption - two_over_ratio * r.v_avg * c_mean, r.v_avg, pend))
-        state, k = (r.a_h, r.b_h, r.a_f, r.b_f), pend
-    return out
+    return [(q.absorption, q.v_avg, q.end) for q in oracle.run_periods(pb, P)]
 
 
 def make_batch(bte, inst, precision=0, tuning=None, tol=1e-6, max_periods=60, confirm=1, **kw):

@@ -7,8 +7,8 @@ import numpy as np
 import pytest
 import scipy.special as sp
 
+import oracle
 from paper_1401_6047_amd import workloads as W
-from test_oracle_pins import continuum_u, tucker
 
 pytestmark = pytest.mark.gpu
 
@@ -49,10 +49,10 @@ def test_b0_frequency_scan_matches_tucker(bte):
         L = int(np.rint(2 * math.pi / (w.omega * dt)))
         P = r["periods"]
         tk = np.arange((P - 1) * L + 1, P * L + 1) * dt
-        v = Q * ratio * np.imag(continuum_u(E_dc, E_w, w.omega, tk))
+        v = Q * ratio * np.imag(oracle.continuum_u(E_dc, E_w, w.omega, tk))
         A_win = (2.0 / ratio) * np.mean((v - v.mean()) * np.cos(w.omega * tk))
         assert abs(r["absorption"] - A_win) <= 2e-4 * abs(A_win) + 2e-6, (w.omega, r, A_win)
-        A_t = tucker(E_dc, E_w, w.omega)
+        A_t = oracle.tucker_absorption(E_dc, E_w, w.omega)
         assert abs(r["absorption"] - A_t) <= 3.0 * abs(A_t) / L + 2e-4 * abs(A_t) + 2e-6, \
             (w.omega, r["absorption"], A_t)
 
@@ -77,7 +77,6 @@ def test_fig4_low_temperature_matches_characteristics(bte, E_dc):
     near 1e-6 of v), the node quadrature of the characteristic average (about
     1e-5 of A) and the 1e-9 stopping test; measured differences reach 1.1e-6
     (5e-5 of the scan's largest A), the bound is about four times that."""
-    import oracle
     rows = []
     for om in FIG4_OMEGAS[E_dc]:
         w = W.Workload(f"fig4_{E_dc}_{om}", nx=120, ny=4000, phiy_min=-6.0, phiy_max=6.0,

@@ -13,7 +13,7 @@ import pytest
 import scipy.special as sp
 
 import oracle
-from test_oracle_pins import continuum_u, tucker
+
 
 
 @pytest.mark.parametrize("mu", [None, 116.0])
@@ -35,10 +35,10 @@ def test_b0_trace_and_tucker(E_dc, E_w, omega):
     mu = 116.0
     t, v = oracle.characteristic_v(E_dc, E_w, omega, 0.0, mu)
     ratio = sp.ive(1, mu) / sp.ive(0, mu)
-    ref = ratio * continuum_u(E_dc, E_w, omega, t).imag
+    ref = ratio * oracle.continuum_u(E_dc, E_w, omega, t).imag
     # fourth-order quadrature in tau at h = 0.01: a few 1e-9
     np.testing.assert_allclose(v, ref, rtol=0, atol=1e-8)
-    ref_A = tucker(E_dc, E_w, omega)
+    ref_A = oracle.tucker_absorption(E_dc, E_w, omega)
     for m in (None, mu):
         A = oracle.characteristic_absorption(E_dc, E_w, omega, 0.0, m)
         assert abs(A - ref_A) < 1e-8 * max(1.0, abs(ref_A)), (m, A, ref_A)

@@ -154,3 +154,50 @@ def test_predict_shape(n):
     x, c = _data(9, n)
     out = mlp.predict(_rand_theta(10), mlp.normalization(x, c), x)
     assert out.shape == (n, 64, 128)
+
+
+def _bf16(a):
+    """Round float64 values to bfloat16 (8 significant bits, nearest-even) by
+    rounding the float32 bit pattern, the way the GPU converts operands."""
+    f = np.asarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    f = (f + 0x7FFF + ((f >> 16) & 1)) & 0xFFFF0000
+    return f.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _emulated_forward(theta, norm, x, bf16):
+    """The GPU's rounding model run on the CPU: layer 1 in float32, the two
+    large products with operands rounded (bf16 or float32) and float32 sums."""
+    p = mlp.unpack(theta)
+    r = _bf16 if bf16 else (lambda a: np.asarray(a, np.float32).astype(np.float64))
+    f32 = np.float32
+    xn = ((x.astype(f32) - norm[0].astype(f32)) / norm[1].astype(f32)).astype(f32)
+    Z1 = (xn @ p["W1"].T.astype(f32) + p["b1"].astype(f32)).astype(np.float64)
+    H1 = mlp.gelu(Z1)
+    Z2 = (r(H1).astype(f32) @ r(p["W2"].T).astype(f32)).astype(np.float64) + p["b2"]
+    H2 = mlp.gelu(Z2)
+    Y = (r(H2).astype(f32) @ r(p["W3"].T).astype(f32)).astype(np.float64) + p["b3"]
+    return Y / norm[2]
+
+
+@pytest.mark.parametrize("bf16", [True, False])
+def test_forward_error_bound_holds_for_the_rounding_model(bf16):
+    """The element-wise bound contains the error of a CPU emulation of the
+    GPU's rounding (operands rounded, float32 sums) and is not vacuous: the
+    emulated error reaches a visible share of it somewhere."""
+    g = np.random.default_rng(5)
+    theta = np.concatenate([g.normal(size=int(np.prod(s))) / np.sqrt(s[-1]) if len(s) == 2
+                            else 0.1 * g.normal(size=s[0]) for _, s in mlp.SHAPES])
+    x = g.normal(size=(24, 5)) * [2, 0.1, 1, 2, 1] + [4, 0.1, 2, 4, 1]
+    c = g.normal(size=(24, 8192)) * 1e-3
+    norm = mlp.normalization(x, c)
+    want = mlp.predict(theta, norm, x).reshape(24, -1)
+    got = _emulated_forward(theta, norm, x, bf16)
+    bound = mlp.predict_error_bound(theta, norm, x, bf16).reshape(24, -1)
+    err = np.abs(got - want)
+    assert np.all(err <= bound)
+    assert (err / bound).max() > (1e-2 if bf16 else 1e-4)
+    # operand rounding dominates in bf16 (2 u_bf16 against 256 u_f32 of
+    # float32 summation): the bf16 bounds are a few hundred times wider
+    other = mlp.predict_error_bound(theta, norm, x, not bf16).reshape(24, -1)
+    ratio = np.median(bound / other)
+    assert (ratio > 100) if bf16 else (ratio < 1e-2)

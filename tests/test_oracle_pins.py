@@ -140,15 +140,7 @@ def test_b0_time_dependent_field_matches_scalar_recurrence():
     np.testing.assert_allclose(r.v_trace, ref, rtol=0, atol=2e-13 * np.abs(ref).max())
 
 
-def tucker(E_dc, E_w, omega, lmax=60):
-    """Absorption at B = 0 in the continuum: sum_l J_l(a)[J_{l+1}(a)+J_{l-1}(a)]
-    xi(E_dc + l omega), a = E_w/omega, xi(x) = x/(1+x^2).  This is the Tucker sum
-    derived from the Fourier system with A defined as <(2 I0/I1) v cos wt>; the
-    paper prints it with an extra factor 2 I1/I0."""
-    a = E_w / omega
-    l = np.arange(-lmax, lmax + 1)
-    x = E_dc + l * omega
-    return float(np.sum(sp.jv(l, a) * (sp.jv(l + 1, a) + sp.jv(l - 1, a)) * x / (1 + x ** 2)))
+tucker = oracle.tucker_absorption
 
 
 def test_tucker_closed_form_values():
@@ -158,17 +150,7 @@ def test_tucker_closed_form_values():
     assert abs(tucker(5.0, 1.0, 1.0) - (-0.0374279998507363)) < 1e-15
 
 
-def continuum_u(E_dc, E_w, omega, t, lmax=30):
-    """Periodic steady state of du/dt = 1 - (1 - i E(t)) u, the harmonic-1
-    amplitude at B = 0 (v_dr = (I1/I0) Im u in the continuum), by Jacobi-Anger:
-    u(t) = sum_{n,l} J_n(a) J_l(a) e^{i(n-l) w t} / (1 - i (E_dc + l w))."""
-    a = E_w / omega
-    l = np.arange(-lmax, lmax + 1)
-    J = sp.jv(l, a)
-    coef_l = J / (1 - 1j * (E_dc + l * omega))
-    ph_n = np.exp(1j * np.outer(t, l) * omega) @ J            # sum_n J_n e^{i n w t}
-    ph_l = np.exp(-1j * np.outer(t, l) * omega) @ coef_l      # sum_l J_l e^{-i l w t}/(...)
-    return ph_n * ph_l
+continuum_u = oracle.continuum_u
 
 
 @pytest.mark.parametrize("E_dc,E_w,omega", [(6.0, 0.1, 2.0), (5.0, 1.0, 1.0), (0.0, 0.5, 3.0)])
@@ -200,6 +182,126 @@ def test_continuum_u_reproduces_tucker():
     t = np.linspace(0, 2 * math.pi / omega, 4001)[:-1]
     A = 2.0 * np.mean(continuum_u(E_dc, E_w, omega, t).imag * np.cos(omega * t))
     assert abs(A - tucker(E_dc, E_w, omega)) < 1e-13
+
+
+def test_tucker_small_signal_limit():
+    """To first order in a = E_w/omega only J_0 ~ 1 and J_{+-1} ~ +-a/2 survive:
+    A -> (E_w / (2 omega)) [xi(E_dc + omega) - xi(E_dc - omega)], xi(x) = x/(1+x^2)
+    (the linear response of the Esaki-Tsu current; the relative error is O(a^2))."""
+    xi = lambda x: x / (1 + x * x)
+    for E_dc, omega in ((0.0, 2.0), (3.0, 1.5), (6.0, 0.7)):
+        E_w = 1e-4
+        a = E_w / omega
+        lin = E_w / (2 * omega) * (xi(E_dc + omega) - xi(E_dc - omega))
+        assert abs(tucker(E_dc, E_w, omega) - lin) < 2 * a * a * abs(lin)
+
+
+def test_continuum_u_solves_the_harmonic_one_equation():
+    """The Jacobi-Anger periodic state equals a direct integration of
+    du/dt = 1 - (1 - i E(t)) u from u = 0 once the e^{-t} transient is gone."""
+    from scipy.integrate import solve_ivp
+    for E_dc, E_w, omega in ((6.0, 0.1, 2.0), (2.0, 1.5, 0.8)):
+        def rhs(t, y):
+            u = y[0] + 1j * y[1]
+            d = 1.0 - (1.0 - 1j * (E_dc + E_w * math.cos(omega * t))) * u
+            return [d.real, d.imag]
+        T = 2 * math.pi / omega
+        t_end = math.ceil(40.0 / T) * T
+        t = t_end - T + np.linspace(0.0, T, 50)
+        sol = solve_ivp(rhs, (0.0, t_end), [0.0, 0.0], method="DOP853", rtol=1e-12,
+                        atol=1e-14, t_eval=t)
+        u_ode = sol.y[0] + 1j * sol.y[1]
+        np.testing.assert_allclose(continuum_u(E_dc, E_w, omega, t), u_ode, rtol=0, atol=1e-9)
+
+
+def test_period_absorption_on_an_exact_period_is_the_plain_average():
+    """With dt = 2 pi / (omega L) a period of L steps is exactly 2 pi / omega
+    and the cosine sums to zero over it, so taking out the period's mean drift
+    velocity changes nothing: A_p equals the oracle's plain window average
+    (Kahan sums in C) over the same steps."""
+    L = 2000
+    omega = 1.7
+    dt = 2 * math.pi / (omega * L)
+    pb = oracle.Problem(nx=16, ny=61, phiy_min=-5, phiy_max=5, E_dc=2.5, E_w=0.4, omega=omega,
+                        B=1.5, mu=1.5, dt=dt)
+    per = oracle.run_periods(pb, 3)
+    assert [q.end for q in per] == [L, 2 * L, 3 * L]
+    r = oracle.run(pb, 3 * L, window=(2 * L, 3 * L))
+    assert abs(per[2].v_avg - r.v_avg) < 1e-13 * abs(r.v_avg)
+    assert abs(per[2].plain - r.absorption) < 1e-12 * abs(r.absorption)
+    assert abs(per[2].absorption - r.absorption) < 1e-11 * abs(r.absorption)
+
+
+def test_period_absorption_b0_matches_the_continuum_over_the_same_steps():
+    """At B = 0 each period's A_p equals the Jacobi-Anger periodic state with its
+    mean taken out, averaged over the same steps (O(dt^2) and the e^{-t}
+    transient), on a window that is not a whole period: the plain average
+    over those steps differs from both by the leak of the dc drift."""
+    omega, dt, mu, E_dc, E_w = 2.0, 2e-3, 2.0, 3.0, 0.5
+    pb = oracle.Problem(nx=16, ny=81, phiy_min=-6, phiy_max=6, E_dc=E_dc, E_w=E_w, omega=omega,
+                        B=0.0, mu=mu, dt=dt)
+    L = oracle.period_steps(omega, dt)
+    assert abs(L * dt - 2 * math.pi / omega) > 0.1 * dt          # not an exact period
+    per = oracle.run_periods(pb, 16)
+    q = per[-1]
+    k = np.arange(q.end - L + 1, q.end + 1)
+    t = k * dt
+    v = np.imag(continuum_u(E_dc, E_w, omega, t))               # in units of (I_1/I_0)
+    c = np.cos(omega * t)
+    A_ref = 2.0 * np.mean((v - v.mean()) * c)
+    assert abs(q.absorption - A_ref) < 2e-5 * abs(A_ref)
+    plain_ref = 2.0 * np.mean(v * c)
+    assert abs(q.plain - plain_ref) < 2e-5 * abs(A_ref)
+    assert abs(plain_ref - A_ref) > 1e-3 * abs(A_ref)           # the leak the reading removes
+
+
+def test_resolution_diagnostics_of_the_equilibrium():
+    """For f0 the diagnostics have closed forms.  Edge mass: a_0 is the thermal
+    Gaussian of Sec. 2, so the edge strips hold its probability between the
+    strip's outer and inner cell faces (the rectangle rule is the midpoint
+    rule there), given by erfc.  Top-harmonic share: a_n is proportional to
+    sigma(n) I_n(mu), and sum over all integer n of I_n(mu)^2 = I_0(2 mu)
+    (Neumann's addition theorem), so the Parseval total is
+    I_0(2 mu) / (2 I_0(mu)^2) in units of the top terms (I_n/I_0)^2."""
+    pb = oracle.Problem(nx=24, ny=641, phiy_min=-3.0, phiy_max=3.0, E_dc=0, E_w=0, omega=0,
+                        B=0, mu=1.0, dt=1e-3, alpha=0.9496)
+    a0 = oracle.equilibrium(pb)
+    edge, top = oracle.resolution_diagnostics(pb, a0, np.zeros_like(a0))
+    w = oracle.edge_width(pb.ny)
+    dphi = (pb.phiy_max - pb.phiy_min) / (pb.ny - 1)
+    s = math.sqrt(pb.mu / 2.0)
+    lo, hi = pb.phiy_min - 0.5 * dphi, pb.phiy_min + (w - 0.5) * dphi   # one strip's faces
+    strip = 0.5 * (sp.erfc(-hi * s) - sp.erfc(-lo * s))                  # P(lo < phi < hi)
+    assert abs(edge - 2 * strip) < 1e-4 * 2 * strip, (edge, 2 * strip)
+    for mu, nx in ((1.0, 16), (10.0, 24), (116.0, 120)):
+        pb = oracle.Problem(nx=nx, ny=81, phiy_min=-6, phiy_max=6, E_dc=0, E_w=0, omega=0, B=0,
+                            mu=mu, dt=1e-3)
+        a0 = oracle.equilibrium(pb)
+        _, top = oracle.resolution_diagnostics(pb, a0, np.zeros_like(a0))
+        h = oracle.top_harmonics(nx)
+        n = np.arange(nx - h, nx)
+        r2 = (sp.ive(n, mu) / sp.ive(0, mu)) ** 2
+        ref = r2.sum() / (0.5 * sp.ive(0, 2 * mu) / sp.ive(0, mu) ** 2)
+        assert abs(top - ref) < 1e-10 * ref, (mu, top, ref)
+
+
+def test_resolution_diagnostics_see_an_unresolved_state():
+    """A state with all its weight in the last harmonic (and b only) has top
+    share 1; one that lives only in the outer phi_y strips has the whole
+    normalisation at the edges; moving the weight inside takes both to 0."""
+    pb = oracle.Problem(nx=16, ny=129, phiy_min=-4, phiy_max=4, E_dc=0, E_w=0, omega=0, B=0,
+                        mu=1.0, dt=1e-3)
+    a = np.zeros((16, 129)); b = np.zeros((16, 129))
+    b[15] = 1.0
+    assert oracle.resolution_diagnostics(pb, a, b)[1] == 1.0
+    b[15] = 0.0; b[5] = 1.0
+    assert oracle.resolution_diagnostics(pb, a, b)[1] == 0.0
+    dphi = 8.0 / 128
+    a[0, :3] = a[0, -3:] = 1.0 / (2 * math.pi * dphi * 6)            # w = 3: unit normalisation
+    edge, _ = oracle.resolution_diagnostics(pb, a, b)
+    assert abs(edge - 1.0) < 1e-14
+    a[0] = 0.0; a[0, 60:66] = 1.0 / (2 * math.pi * dphi * 6)
+    assert oracle.resolution_diagnostics(pb, a, b)[0] == 0.0
 
 
 # ---------------------------------------------------------------------------
