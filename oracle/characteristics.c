@@ -83,18 +83,17 @@ int oracle_characteristic_v(double E_dc, double E_w, double omega, double B,
     int nt = 1;
     (void)n_threads;
 #endif
-    double* part = (double*)calloc((size_t)nt * (size_t)n_launch, sizeof(double));
+    /* row j holds the contributions of the points launched at t_j to every
+       sample time; the rows are summed in order afterwards, so the result
+       does not depend on the thread count or on which thread ran which j */
+    double* part = (double*)calloc((size_t)n_launch * (size_t)n_launch, sizeof(double));
     if (!part) { free(field); return -3; }
     int bad = 0;
 #ifdef _OPENMP
-#pragma omp parallel for num_threads(nt) schedule(dynamic, 1)
+#pragma omp parallel for num_threads(nt) schedule(dynamic, 1) reduction(|: bad)
 #endif
     for (int32_t j = 0; j < n_launch; ++j) {
-#ifdef _OPENMP
-        double* acc = part + (size_t)omp_get_thread_num() * n_launch;
-#else
-        double* acc = part;
-#endif
+        double* acc = part + (size_t)j * n_launch;
         for (int32_t q = 0; q < n_nodes; ++q) {
             double x = x0[q], y = y0[q];
             /* tau = 0: trapezoid end weight 1/2, and the Euler-Maclaurin
@@ -123,7 +122,7 @@ int oracle_characteristic_v(double E_dc, double E_w, double omega, double B,
     }
     for (int32_t i = 0; i < n_launch; ++i) {
         double s = 0.0;
-        for (int t = 0; t < nt; ++t) s += part[(size_t)t * n_launch + i];
+        for (int32_t j = 0; j < n_launch; ++j) s += part[(size_t)j * n_launch + i];
         v[i] = h * s;
     }
     free(part);
