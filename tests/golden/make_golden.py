@@ -6,6 +6,7 @@ directory named after the workload and step count.
 
     python tests/golden/make_golden.py crossed            # 128 x 1001, full 100 periods
     python tests/golden/make_golden.py large_prefix       # 512 x 8193, first 2000 steps
+    python tests/golden/make_golden.py table1             # 120 x 4000, the paper's Table-1 run
 """
 from __future__ import annotations
 
@@ -77,6 +78,12 @@ def main(argv):
     elif which == "large_prefix":
         w = W.LARGE
         run_and_store(w, 2000, (1000, 2000), f"{w.name}_2000", threads)
+    elif which == "table1":
+        # Sec. 7, Table 1: 1e5 steps (t = 10) from f0; absorption over the
+        # last five ac periods of round(T/dt) steps each
+        w = W.TABLE1
+        L = int(np.rint(2.0 * np.pi / (w.omega * w.dt)))
+        run_and_store(w, w.n_steps, (w.n_steps - 5 * L, w.n_steps), f"{w.name}_1e5", threads)
     else:
         raise SystemExit(f"unknown golden set {which}")
 
