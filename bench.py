@@ -69,8 +69,8 @@ def parse():
     ap.add_argument("--waves-per-block", type=int, default=0)
     ap.add_argument("--sweep", type=int, default=192,
                     help="instances of the batched-sweep measurement (0: skip)")
-    ap.add_argument("--sweep-fp64", type=int, default=8,
-                    help="of those, how many the plain FP64 solver also runs")
+    ap.add_argument("--sweep-fp64", type=int, default=12,
+                    help="draws the plain FP64 solver also runs (split evenly over the mu classes)")
     ap.add_argument("--warm-train", type=int, default=2048,
                     help="coarse-grid training states for the warm-started sweep (0: no warm run)")
     ap.add_argument("--reconstruct", type=int, default=512,
@@ -92,6 +92,10 @@ def time_solver(bte, torch, w, precision, kernel, steps, warmup, autotune=True, 
     else:
         s.set_tuning(kernel=max(kernel, 0))
     s.step(warmup)
+    # the timed steps are the averaging window: every one of them takes the
+    # drift-velocity and absorption accumulation (outside the window the
+    # kernels skip it)
+    s.set_window(warmup, warmup + steps)
     torch.cuda.synchronize()
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
@@ -104,6 +108,8 @@ def time_solver(bte, torch, w, precision, kernel, steps, warmup, autotune=True, 
     wall = time.perf_counter() - t0
     ms = start.elapsed_time(stop)
     obs = s.observables()
+    if obs.n_avg != steps:
+        raise RuntimeError(f"window holds {obs.n_avg} steps, expected {steps}")
     tune = s.tuning()
     elem = 4 if precision == 1 else 8
     form = tune.kernel
@@ -118,6 +124,7 @@ def time_solver(bte, torch, w, precision, kernel, steps, warmup, autotune=True, 
         "kernel": KERNEL_NAMES[form], "steps_per_launch": {2: 2, 3: 3}.get(form, 1),
         "achieved_GBs": bytes_per_launch / avg_launch_s / 1e9,
         "status": int(obs.status), "v_dr": obs.v_dr, "norm": obs.norm,
+        "window_steps": int(obs.n_avg), "v_avg": obs.v_avg, "absorption": obs.absorption,
         "autotune_best_us_per_step": tuned_us,
         "tuning": {"kernel": tune.kernel, "rows_per_wave": tune.rows_per_wave,
                    "waves_per_block": tune.waves_per_block, "graph_steps": tune.graph_steps},
@@ -196,33 +203,65 @@ def counter_traffic(kernel, precision, tuning):
     return None
 
 
+def cpu_model():
+    """The host CPU's model name (first 'model name' line of /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
 def cpu_baseline(w, sample_steps):
+    """The FP64 oracle on a bounded sample of the workload, with all host
+    threads and with one thread (the paper's single-thread baseline style)."""
     import oracle
     pb = oracle.Problem(nx=w.nx, ny=w.ny, phiy_min=w.phiy_min, phiy_max=w.phiy_max,
                         E_dc=w.E_dc, E_w=w.E_w, omega=w.omega, B=w.B, mu=w.mu, dt=w.dt,
                         alpha=w.alpha)
     threads = oracle.max_threads()
     if sample_steps <= 0:
-        # about 10-20 s of oracle work at ~2.5e7 cell-steps/s per thread
-        sample_steps = max(4, int(15 * 2.5e7 * threads / (w.nx * w.ny)))
+        # about 10-15 s of oracle work at ~2.5e7 cell-steps/s per thread
+        sample_steps = max(4, int(12 * 2.5e7 * threads / (w.nx * w.ny)))
     oracle.run(pb, 1)                 # build/load, first touch
     t0 = time.perf_counter()
     oracle.run(pb, sample_steps)
     secs = time.perf_counter() - t0
+    one_steps = max(2, sample_steps // max(threads, 1))
+    t0 = time.perf_counter()
+    oracle.run(pb, one_steps, n_threads=1)
+    secs1 = time.perf_counter() - t0
     return {"value": w.nx * w.ny * sample_steps / secs, "unit": "grid-point updates/s",
-            "cores": threads, "kind": "oracle",
+            "cores": threads, "kind": "oracle", "cpu_model": cpu_model(),
             "sample": f"{w.name}: {sample_steps} whole steps from f0 (incl. start-up), "
-                      f"FP64, {secs:.1f} s, OpenMP threads={threads}"}
+                      f"FP64, {secs:.1f} s, OpenMP threads={threads}",
+            "one_thread": {"value": w.nx * w.ny * one_steps / secs1, "cores": 1,
+                           "sample": f"{w.name}: {one_steps} whole steps from f0, FP64, "
+                                     f"{secs1:.1f} s, 1 thread"}}
+
+
+def stratified(draws, per_class):
+    """Indices of the first `per_class` draws of each temperature class."""
+    idx = []
+    for mu in sorted({w.mu for w in draws}):
+        idx += [i for i, w in enumerate(draws) if w.mu == mu][:per_class]
+    return sorted(idx)
 
 
 def sweep_bench(bte, torch, n, n_fp64, n_train, log):
-    """Instances per hour of the parameter sweep: the plain FP64 solver (one
-    instance at a time, per-period host check) on the first n_fp64 draws, the
-    batched FP32-bulk sweep (the library's default schedule: wide) on all n,
-    cold and warm-started from the trained network.  Every run stops once
-    |A_p - A_{p-1}| < 1e-6 holds for two consecutive periods (a single test
-    can stop on a rotating transient); the absorption of the batched runs is
-    compared with the FP64 solver's on the common draws."""
+    """Instances per hour of the parameter sweep.  The plain FP64 solver runs
+    one instance after another (per-period host check) on a temperature-
+    stratified subset of the draws, with its launch shape tuned once per N_y
+    class before the clock starts; the batched FP32-bulk sweep (the library's
+    default schedule: wide) runs the same subset, for a like-for-like ratio,
+    and then all n draws, cold and warm-started from the trained network.
+    Every run stops once |A_p - A_{p-1}| < 1e-6 holds for two consecutive
+    periods (a single test can stop on a rotating transient); the absorption
+    of the batched runs is compared with the FP64 solver's on the subset."""
     from paper_1401_6047_amd import workloads as W
     from paper_1401_6047_amd import warmstart
     draws = W.sweep_draws(n)
@@ -231,27 +270,47 @@ def sweep_bench(bte, torch, n, n_fp64, n_train, log):
                        f"E_w = 0.1, mu in {{0.25,1,4}} -> N_y 401/801/1601, N_x {nx}, "
                        f"phi_y in [-{phi:g},{phi:g}], dt {dt:g}, tol 1e-6 over 2 periods",
            "unit": "instances/hour"}
-    # plain FP64 solver, one instance after another
+    sub_idx = stratified(draws, max(1, n_fp64 // 3))
+    sub = [draws[i] for i in sub_idx]
+    # plain FP64 solver: one launch shape per N_y class, tuned before timing
+    tunings = {}
+    for w in sub:
+        if w.ny not in tunings:
+            s = bte.Solver.from_workload(w)
+            tunings[w.ny], _ = s.autotune(target_ms=0.5)
+            s.close()
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     ref = []
-    for w in draws[:n_fp64]:
+    for w in sub:
         s = bte.Solver.from_workload(w)
-        s.autotune(target_ms=0.5)
+        bte.bte_set_tuning(s.handle, tunings[w.ny])
         ref.append(s.run_periods(tol=1e-6, max_periods=400, confirm=2))
         s.close()
     torch.cuda.synchronize()
     t_fp64 = time.perf_counter() - t0
-    log(f"  fp64 solver: {n_fp64} instances in {t_fp64:.1f} s")
+    log(f"  fp64 solver: {len(sub)} instances in {t_fp64:.1f} s")
+    sub_res, t_sub = warmstart.sweep(sub, nx, phi, dt, log=log, confirm=2)
+    log(f"  batched fp32 on the same {len(sub)} instances: {t_sub:.1f} s")
     cold, t_cold = warmstart.sweep(draws, nx, phi, dt, log=log, confirm=2)
     log(f"  batched fp32 cold: {n} instances in {t_cold:.1f} s")
-    dA = [abs(a["absorption"] - b["absorption"]) for a, b in zip(ref, cold[:n_fp64])]
-    out["fp64_solver"] = {"instances": n_fp64, "wall_s": t_fp64,
-                          "value": n_fp64 / t_fp64 * 3600,
-                          "periods_mean": sum(r["periods"] for r in ref) / n_fp64}
+
+    def max_dA(res):
+        return max(abs(a["absorption"] - b["absorption"]) for a, b in zip(ref, res))
+
+    out["fp64_solver"] = {"instances": len(sub), "wall_s": t_fp64,
+                          "value": len(sub) / t_fp64 * 3600,
+                          "periods_mean": sum(r["periods"] for r in ref) / len(sub),
+                          "draws": "first %d of each mu class" % max(1, n_fp64 // 3),
+                          "tunings": {str(k): [t.kernel, t.rows_per_wave, t.waves_per_block]
+                                      for k, t in tunings.items()}}
+    out["batched_fp32_same_draws"] = {"instances": len(sub), "wall_s": t_sub,
+                                      "value": len(sub) / t_sub * 3600,
+                                      "abs_dA_vs_fp64_max": max_dA(sub_res)}
     out["batched_fp32"] = {"instances": n, "wall_s": t_cold, "value": n / t_cold * 3600,
                            "periods_mean": sum(r["periods"] for r in cold) / n,
                            "converged": sum(r["converged"] for r in cold),
-                           "abs_dA_vs_fp64_max": max(dA)}
+                           "abs_dA_vs_fp64_max": max_dA([cold[i] for i in sub_idx])}
     if n_train > 0:
         train = warmstart.coarse_draws(n_train, W.SWEEP_SEED + 101)
         t0 = time.perf_counter()
@@ -272,19 +331,22 @@ def sweep_bench(bte, torch, n, n_fp64, n_train, log):
         warm, t_warm = warmstart.sweep(draws, nx, phi, dt, warm=pred, log=log, confirm=2)
         log(f"  batched fp32 warm: {n} instances in {t_warm:.1f} s "
             f"(+{t_inf * 1e3:.0f} ms inference; training data + training {t_prep:.1f} s)")
-        dAw = [abs(a["absorption"] - b["absorption"]) for a, b in zip(ref, warm[:n_fp64])]
+        pc = sum(r["periods"] for r in cold)
+        pw = sum(r["periods"] for r in warm)
         out["batched_fp32_warm"] = {
             "instances": n, "wall_s": t_warm + t_inf, "value": n / (t_warm + t_inf) * 3600,
-            "periods_mean": sum(r["periods"] for r in warm) / n,
+            "periods_mean": pw / n, "periods_saved_frac": 1.0 - pw / pc,
+            "wall_saved_frac": 1.0 - (t_warm + t_inf) / t_cold,
             "converged": sum(r["converged"] for r in warm),
-            "abs_dA_vs_fp64_max": max(dAw),
+            "abs_dA_vs_fp64_max": max_dA([warm[i] for i in sub_idx]),
             "abs_dA_vs_cold_max": max(abs(a["absorption"] - b["absorption"])
                                       for a, b in zip(cold, warm)),
             "network": {"train_states": len(keep), "train_grid": "N_x 48, N_y 101/201/401, dt 1e-3",
                         "epochs": 40, "final_loss": hist[-1], "prep_s": t_prep}}
     best = out.get("batched_fp32_warm", out["batched_fp32"])
     out["value"] = best["value"]
-    out["vs_fp64_solver"] = best["value"] / out["fp64_solver"]["value"]
+    out["vs_fp64_solver_same_draws"] = (out["batched_fp32_same_draws"]["value"]
+                                        / out["fp64_solver"]["value"])
     return out
 
 

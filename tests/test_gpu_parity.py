@@ -257,26 +257,145 @@ def check_against_golden(o, st, g, w, tol_obs, tol_state):
         assert err <= tol_state * scale, (key, err)
 
 
-@pytest.mark.parametrize("precision,tol_obs,tol_state", [(0, 1e-10, 1e-11), (1, 1e-5, 1e-5)],
-                         ids=["fp64", "fp32bulk"])
-def test_crossed_full_length_vs_golden(bte, precision, tol_obs, tol_state):
+PRECISIONS = [(0, 1e-10, 1e-11), (1, 1e-5, 1e-5)]
+
+
+def run_tuned(bte, w, n_steps, window, precision, tuning):
+    """Like run_gpu, with tuning = "auto" running the autotuner first (the
+    benchmark's own call, so the form and shape it times are the ones
+    compared) and printing what it picked."""
+    s = bte.Solver.from_workload(w, precision=precision)
+    if tuning == "auto":
+        s.autotune()
+    elif tuning:
+        s.set_tuning(**tuning)
+    t = s.tuning()
+    print(f"{w.name} precision={precision}: kernel {t.kernel} R{t.rows_per_wave} "
+          f"W{t.waves_per_block} graph {t.graph_steps}", flush=True)
+    s.set_window(*window)
+    s.step(n_steps)
+    o = s.observables()
+    st = s.state()
+    s.close()
+    return o, st
+
+
+@pytest.mark.parametrize("tuning", [None, "auto"], ids=["default", "autotuned"])
+@pytest.mark.parametrize("precision,tol_obs,tol_state", PRECISIONS, ids=["fp64", "fp32bulk"])
+def test_crossed_full_length_vs_golden(bte, precision, tol_obs, tol_state, tuning):
     g = load_golden("crossed_128x1001_full.json")
     w = W.CROSSED
-    o, st = run_gpu(bte, w, w.n_steps, window=w.window, precision=precision)
+    o, st = run_tuned(bte, w, w.n_steps, w.window, precision, tuning)
     print(f"crossed full precision={precision}: v_avg={o.v_avg!r} A={o.absorption!r} "
           f"(oracle {g['obs']['v_avg']!r}, {g['obs']['absorption']!r})", flush=True)
     check_against_golden(o, st, g, w, tol_obs, tol_state)
 
 
-@pytest.mark.parametrize("precision,tol_obs,tol_state", [(0, 1e-10, 1e-11), (1, 1e-5, 1e-5)],
-                         ids=["fp64", "fp32bulk"])
-def test_large_prefix_vs_golden(bte, precision, tol_obs, tol_state):
-    """512 x 8193 at full size, in the default launch configuration the
-    benchmark times, against the oracle's first 2000 steps."""
+# 512 x 8193: the library default, the autotuner's live pick, and the forms
+# and shapes it picks on this grid (FP64: three-step 43/4; FP32 bulk: two-step
+# 26/2, and the three-step form), each with 48-step graph replays.
+LARGE_TUNINGS = [
+    (0, None), (1, None), (0, "auto"), (1, "auto"),
+    (0, dict(kernel=3, rows_per_wave=43, waves_per_block=4, graph_steps=48)),
+    (0, dict(kernel=2, rows_per_wave=40, waves_per_block=4, graph_steps=48)),
+    (1, dict(kernel=2, rows_per_wave=26, waves_per_block=2, graph_steps=48)),
+    (1, dict(kernel=3, rows_per_wave=43, waves_per_block=4, graph_steps=48)),
+    (1, dict(kernel=3, rows_per_wave=26, waves_per_block=2, graph_steps=0)),
+]
+
+
+@pytest.mark.parametrize("precision,tuning", LARGE_TUNINGS,
+                         ids=lambda v: v if isinstance(v, str) else
+                         ("default" if v is None else
+                          ("fp64", "fp32bulk")[v] if isinstance(v, int) else
+                          "-".join(f"{k}{x}" for k, x in v.items())))
+def test_large_prefix_vs_golden(bte, precision, tuning):
+    """512 x 8193 at full size against the oracle's first 2000 steps, in the
+    launch configurations the benchmark times."""
+    _, tol_obs, tol_state = PRECISIONS[precision]
     g = load_golden("large_512x8193_2000.json")
     w = W.LARGE
-    o, st = run_gpu(bte, w, g["n_steps"], window=tuple(g["window"]), precision=precision)
+    o, st = run_tuned(bte, w, g["n_steps"], tuple(g["window"]), precision, tuning)
     check_against_golden(o, st, g, w, tol_obs, tol_state)
+
+
+@pytest.mark.parametrize("tuning", [None, "auto",
+                                    dict(kernel=3, rows_per_wave=20, waves_per_block=4,
+                                         graph_steps=0)],
+                         ids=["default", "autotuned", "k3-R20-W4-direct"])
+@pytest.mark.parametrize("precision,tol_obs,tol_state", PRECISIONS, ids=["fp64", "fp32bulk"])
+def test_table1_vs_golden(bte, precision, tol_obs, tol_state, tuning):
+    """The paper's Table-1 run (Sec. 7: 120 harmonics x 4000 phi_y points on
+    [-6, 6], mu = 116, alpha = 0.9496, E_dc = 7, E_w = 0.1, omega = 10, B = 4,
+    dt = 1e-4, 10^5 steps from f0) against the oracle's stored run."""
+    g = load_golden("table1_120x4000_1e5.json")
+    w = W.TABLE1
+    assert g["params"]["alpha"] == w.alpha and g["params"]["ny"] == w.ny
+    o, st = run_tuned(bte, w, g["n_steps"], tuple(g["window"]), precision, tuning)
+    print(f"table1 precision={precision}: v_avg={o.v_avg!r} A={o.absorption!r} "
+          f"(oracle {g['obs']['v_avg']!r}, {g['obs']['absorption']!r})", flush=True)
+    check_against_golden(o, st, g, w, tol_obs, tol_state)
+
+
+# FP32 bulk stores with stochastic rounding seeded by the step and the
+# plane, so its bits depend on how steps are grouped into launches: every
+# multi-step form, graph length and remainder rule is compared with the
+# oracle on its own.
+FP32_TUNINGS = [
+    dict(kernel=2),
+    dict(kernel=2, rows_per_wave=26, waves_per_block=2, graph_steps=48),
+    dict(kernel=2, rows_per_wave=5, waves_per_block=1, graph_steps=0),
+    dict(kernel=3),
+    dict(kernel=3, rows_per_wave=43, waves_per_block=4, graph_steps=48),
+    dict(kernel=3, rows_per_wave=7, waves_per_block=2, graph_steps=10),
+    dict(kernel=3, rows_per_wave=54, waves_per_block=1, graph_steps=0),
+    dict(kernel=1, rows_per_wave=9, waves_per_block=4, graph_steps=4),
+]
+
+
+@pytest.mark.parametrize("tuning", FP32_TUNINGS,
+                         ids=lambda t: "-".join(f"{k}{v}" for k, v in t.items()))
+def test_crossed_fp32_multistep_matches_oracle(bte, crossed_ref, tuning):
+    w = W.CROSSED
+    o, st = run_gpu(bte, w, 2000, window=(1000, 2000), precision=bte.BTE_FP32_BULK,
+                    tuning=tuning)
+    r = crossed_ref
+    assert o.n_avg == r.K == 1000
+    assert rel(o.v_dr, r.v) < 1e-5
+    assert rel(o.v_avg, r.v_avg) < 1e-5
+    assert rel(o.absorption, r.absorption, 1e-2 * w.E_w) < 1e-5
+    assert_state_close(st, oracle_state(r), 1e-5, str(tuning))
+
+
+@pytest.fixture(scope="module")
+def crossed_odd_ref():
+    return oracle.run(problem(W.CROSSED), 1001, window=(500, 1001))
+
+
+# 1001 steps: direct launches end in a two-step remainder (three-step form)
+# or a one-step one (two-step form); 10-step graphs hold a one-step launch.
+ODD_TUNINGS = [
+    dict(kernel=3, rows_per_wave=11, waves_per_block=4, graph_steps=0),
+    dict(kernel=3, rows_per_wave=11, waves_per_block=4, graph_steps=10),
+    dict(kernel=3, rows_per_wave=11, waves_per_block=4, graph_steps=4),
+    dict(kernel=2, rows_per_wave=11, waves_per_block=2, graph_steps=0),
+    dict(kernel=2, rows_per_wave=11, waves_per_block=2, graph_steps=6),
+]
+
+
+@pytest.mark.parametrize("tuning", ODD_TUNINGS,
+                         ids=lambda t: "-".join(f"{k}{v}" for k, v in t.items()))
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "fp32bulk"])
+def test_crossed_odd_step_count_remainders(bte, crossed_odd_ref, tuning, precision):
+    w = W.CROSSED
+    tol = 1e-10 if precision == 0 else 1e-5
+    o, st = run_gpu(bte, w, 1001, window=(500, 1001), precision=precision, tuning=tuning)
+    r = crossed_odd_ref
+    assert o.step == 1001 and o.n_avg == r.K == 501
+    assert rel(o.v_dr, r.v) < tol
+    assert rel(o.v_avg, r.v_avg) < tol
+    assert rel(o.absorption, r.absorption, 1e-2 * w.E_w) < tol
+    assert_state_close(st, oracle_state(r), 1e-12 if precision == 0 else 1e-5, str(tuning))
 
 
 def test_autotuner_returns_valid_shape_with_identical_results(bte):
