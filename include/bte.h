@@ -118,6 +118,16 @@ typedef struct {
                             the leak of the dc drift into a window that is not
                             a whole number of periods (identical on exact
                             periods, where S_c = 0) */
+    /* Resolution diagnostics of the whole grid at step k.  Both should stay
+       small; when they do not, the phi_y box or the harmonic count is too
+       small for the run. */
+    double edge_mass;    /* the Sec. 2 normalisation integral 2 pi sqrt(alpha) dphi
+                            sum |a_0(m)| taken over the outer max(1, ceil(N_y/64))
+                            phi_y points at each end of the box */
+    double top_harm_mass;/* share of the integral of f^2 over the Brillouin zone and
+                            the box (Parseval: 2 a_0^2 + sum_{n>=1} a_n^2 + b_n^2,
+                            summed over phi_y) held by the top max(1, N_x/8)
+                            harmonics */
     int32_t status;      /* BTE_OK or BTE_EUNSTABLE */
     int32_t reserved;
 } bte_obs;
@@ -142,14 +152,24 @@ bte_status bte_create(const bte_grid* grid, const bte_params* params, void* work
    with coupling from the fractional grid, then fractional k+1/2 -> k+3/2
    with coupling from the new whole grid).  Steps whose new index k+1 lies in
    the averaging window add b_1(m) and b_1(m) cos(w (k+1) dt) to FP64
-   per-phi_y accumulators.  Queues work only. */
+   per-phi_y accumulators.  Queues work only.
+   Stability: after every captured run of steps (each graph replay) and every
+   run of direct launches, the device checks the state's norm and drift
+   velocity and, when either is not finite or the norm has drifted by more
+   than 1e-2 of its initial value (the norm-deviation bound reported in the
+   paper's Sec. 4), sets a sticky flag in host-visible memory.  Every later
+   bte_step reads that flag without synchronising and returns BTE_EUNSTABLE,
+   queueing nothing, once the device has set it; bte_set_state clears it. */
 bte_status bte_step(bte_solver* s, int64_t n_steps);
 
 /* Set the averaging window to steps k with lo < k <= hi and clear the
    accumulators.  Steps already taken are not re-counted. */
 bte_status bte_set_window(bte_solver* s, int64_t lo, int64_t hi);
 
-/* Reduce and return the observables of the current state (synchronises). */
+/* Reduce and return the observables of the current state (synchronises).
+   Flags the handle unstable (status BTE_EUNSTABLE, sticky) when an
+   observable or the state's f^2 integral is not finite or the norm has
+   drifted by more than 1e-2 of its initial value. */
 bte_status bte_observables(bte_solver* s, bte_obs* out);
 
 /* Copy the state out as four [N_x][N_y] FP64 host arrays (whole grid a, b at
@@ -343,6 +363,19 @@ bte_status bte_batch_results(bte_batch* b, bte_result* out);
 bte_status bte_batch_get_tuning(const bte_batch* b, bte_batch_tuning* t);
 
 void bte_batch_destroy(bte_batch* b);
+
+/* The sweep's stopping rule on one solver: run whole ac periods of
+   L = round(2 pi / (omega dt)) steps from the current step k0 (period p
+   covers k0 + (p-1) L < k <= k0 + p L; k0 = 0 starts at phase 0 of the
+   field), take each period's absorption as bte_obs.absorption_cov over it,
+   and stop when `confirm` consecutive periods each change it by less than
+   `tol` (absolute, with p >= min_periods >= 2) or after max_periods periods.
+   The averaging window is reset for every period.  Fills *out as
+   bte_batch_results does (steps: whole steps taken by this call); an
+   unstable run ends with out->status = BTE_EUNSTABLE and BTE_OK returned.
+   Synchronises once per period.  BTE_EINVAL for omega = 0 or bad limits. */
+bte_status bte_run_periods(bte_solver* s, double tol, int32_t min_periods, int32_t max_periods,
+                           int32_t confirm, bte_result* out);
 
 /* Destroy the handle; frees what the library allocated.  NULL is a no-op. */
 void bte_destroy(bte_solver* s);

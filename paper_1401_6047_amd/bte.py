@@ -50,7 +50,8 @@ class bte_obs(ctypes.Structure):
                 ("n_avg", ctypes.c_int64), ("S_v", ctypes.c_double),
                 ("S_vc", ctypes.c_double), ("v_avg", ctypes.c_double),
                 ("absorption", ctypes.c_double), ("S_c", ctypes.c_double),
-                ("absorption_cov", ctypes.c_double), ("status", ctypes.c_int32),
+                ("absorption_cov", ctypes.c_double), ("edge_mass", ctypes.c_double),
+                ("top_harm_mass", ctypes.c_double), ("status", ctypes.c_int32),
                 ("reserved", ctypes.c_int32)]
 
 
@@ -126,6 +127,8 @@ def _load():
         "bte_batch_results": ([vp, P(bte_result)], ctypes.c_int),
         "bte_batch_get_tuning": ([vp, P(bte_batch_tuning)], ctypes.c_int),
         "bte_batch_destroy": ([vp], None),
+        "bte_run_periods": ([vp, ctypes.c_double, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                             P(bte_result)], ctypes.c_int),
         "bte_destroy": ([vp], None),
         "bte_last_error": ([], ctypes.c_char_p),
         "bte_version": ([], ctypes.c_char_p),
@@ -321,6 +324,15 @@ def bte_batch_get_tuning(h: int) -> bte_batch_tuning:
     return t
 
 
+def bte_run_periods(h: int, tol: float, min_periods: int, max_periods: int,
+                    confirm: int) -> bte_result:
+    r = bte_result()
+    _check(_lib.bte_run_periods(ctypes.c_void_p(h), float(tol), int(min_periods),
+                                int(max_periods), int(confirm), ctypes.byref(r)),
+           "bte_run_periods")
+    return r
+
+
 def bte_batch_destroy(h: int):
     _lib.bte_batch_destroy(ctypes.c_void_p(h))
 
@@ -406,36 +418,13 @@ class Solver:
         return bte_get_tuning(self.handle)
 
     def run_periods(self, tol=1e-6, min_periods=2, max_periods=400, confirm=1):
-        """Advance whole ac periods from a fresh solver (step 0 = phase 0) until
-        the per-period absorption (bte_obs.absorption_cov) changes by less than
-        `tol` between consecutive periods: the batched sweep's criterion, period
-        p covering steps ((p-1) L, p L] with L = round(T/dt).  Returns a dict
+        """bte_run_periods: whole ac periods from the current step until the
+        per-period absorption changes by less than `tol` on `confirm`
+        consecutive periods (the batched sweep's criterion).  Returns a dict
         shaped like the entries of Batch.results()."""
-        import math
-        L = max(1, int(round(2.0 * math.pi / (self.params.omega * self.params.dt))))
-        k, p, prev, run_ok = 0, 0, None, 0
-        out = dict(absorption=0.0, v_avg=0.0, dA=0.0, steps=0, periods=0, converged=0,
-                   status=BTE_OK)
-        while True:
-            p += 1
-            end = p * L
-            self.set_window(k, end)
-            self.step(end - k)
-            k = end
-            o = self.observables()
-            dA = abs(o.absorption_cov - prev) if prev is not None else 0.0
-            out.update(absorption=o.absorption_cov, v_avg=o.v_avg, dA=dA, steps=k, periods=p,
-                       status=int(o.status))
-            if o.status != BTE_OK or not math.isfinite(o.absorption_cov):
-                break
-            run_ok = run_ok + 1 if (p > 1 and dA < tol) else 0
-            if p >= min_periods and run_ok >= confirm:
-                out["converged"] = 1
-                break
-            if p >= max_periods:
-                break
-            prev = o.absorption_cov
-        return out
+        x = bte_run_periods(self.handle, tol, min_periods, max_periods, confirm)
+        return dict(absorption=x.absorption, v_avg=x.v_avg, dA=x.dA, steps=x.steps,
+                    periods=x.periods, converged=x.converged, status=x.status)
 
     def reconstruct(self, n_phix: int, out=None):
         """f(phi_x, phi_y) of the current whole-grid state on x_j = -pi +

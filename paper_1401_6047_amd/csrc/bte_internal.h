@@ -41,7 +41,7 @@ struct Ctl {
     int64_t k;        // whole step of the current state
     int64_t win_lo;   // averaging window: win_lo < k+1 <= win_hi
     int64_t win_hi;
-    int64_t pad;
+    double norm_ref;  // sum_m a_0(m) of the initial state (stability check)
 };
 
 // Per-solver scalars, fixed at creation.
@@ -118,10 +118,27 @@ hipError_t launch_init_equilibrium(const Consts& cs, T* a, T* b, const double* s
 // ctl->k += n (one thread, vector store).
 hipError_t launch_advance_counter(Ctl* ctl, int64_t n, hipStream_t st);
 
-// Deterministic reduction: out[0] = sum_m a_h[0][m], out[1] = sum_m b_h[1][m],
-// out[2] = sum_m acc_v[m], out[3] = sum_m acc_vc[m].
+// Observables of a whole-grid state, reduced in a fixed order (deterministic):
+// one workgroup per harmonic row (plus one for the window sums) writes its
+// partial sums to `part` (3 * (nx + 1) doubles), then one workgroup combines
+// them into out[0..6]:
+//   out[0] = sum_m a_0(m)            out[1] = sum_m b_1(m)
+//   out[2] = sum_m acc_v(m)          out[3] = sum_m acc_vc(m)   (0 if acc_v is NULL)
+//   out[4] = sum over the edge strips (edge_w points each side) of |a_0(m)|
+//   out[5] = sum_m [2 a_0^2 + sum_{n>=1} (a_n^2 + b_n^2)]
+//   out[6] = the same sum over harmonics n >= top_from only.
+// a_h, b_h point at logical (0, 0) of planes with row stride cs.ld.
+constexpr int kObsOut = 7;
 template <typename T>
 hipError_t launch_reduce_obs(const Consts& cs, const T* a_h, const T* b_h, const double* acc_v,
-                             const double* acc_vc, double* out, hipStream_t st);
+                             const double* acc_vc, int edge_w, int top_from, double* part,
+                             double* out, hipStream_t st);
+
+// Stability check of the state after a run of steps: if sum_m a_0(m) or
+// sum_m b_1(m) is not finite, or sum_m a_0 differs from ctl->norm_ref by more
+// than 1e-2 of it, store 1 into *flag (host-visible memory, system scope).
+template <typename T>
+hipError_t launch_check_stable(const Consts& cs, const T* a_h, const T* b_h, const Ctl* ctl,
+                               int* flag, hipStream_t st);
 
 }  // namespace bte

@@ -113,34 +113,112 @@ __global__ void k_advance_counter(Ctl* ctl, int64_t n)
     if (threadIdx.x == 0 && blockIdx.x == 0) ctl->k += n;
 }
 
-constexpr int kReduceThreads = 1024;
+// ---- reductions ----------------------------------------------------------------
+constexpr int kRedThreads = 256;
+
+// Sum of v over the workgroup in a fixed order: a butterfly of wavefront
+// shuffles (every lane ends with the same bits: each level adds the same two
+// partial sums, only in swapped order), then the wavefront sums in order
+// through LDS.  Every thread returns the total.
+__device__ __forceinline__ double block_sum(double v, double* lds)
+{
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    const int w = threadIdx.x / kWave;
+    if ((threadIdx.x & (kWave - 1)) == 0) lds[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int i = 0; i < static_cast<int>(blockDim.x / kWave); ++i) s += lds[i];
+    __syncthreads();
+    return s;
+}
+
+// Partial sums of one harmonic row (block n < nx) or of the window
+// accumulators (block nx): part[3 n .. 3 n + 2] = (energy, x, y) with
+//   row 0: (sum 2 a_0^2, sum a_0, sum over the edge strips of |a_0|)
+//   row 1: (sum a_1^2 + b_1^2, sum b_1, 0), other rows (sum a_n^2 + b_n^2, 0, 0)
+//   block nx: (0, sum acc_v, sum acc_vc).
+template <typename T>
+__global__ __launch_bounds__(kRedThreads) void k_obs_rows(Consts cs, const T* a_h, const T* b_h,
+                                                          const double* acc_v,
+                                                          const double* acc_vc, int edge_w,
+                                                          double* part)
+{
+    __shared__ double lds[kRedThreads / kWave];
+    const int n = blockIdx.x;
+    double e = 0.0, x = 0.0, y = 0.0;
+    if (n < cs.nx) {
+        const T* ar = a_h + static_cast<ptrdiff_t>(n) * cs.ld;
+        const T* br = b_h + static_cast<ptrdiff_t>(n) * cs.ld;
+        for (int m = threadIdx.x; m < cs.ny; m += kRedThreads) {
+            const double a = static_cast<double>(ar[m]);
+            if (n == 0) {
+                e += 2.0 * (a * a);
+                x += a;
+                if (m < edge_w || m >= cs.ny - edge_w) y += fabs(a);
+            } else {
+                const double b = static_cast<double>(br[m]);
+                e += a * a + b * b;
+                if (n == 1) x += b;
+            }
+        }
+    } else if (acc_v) {
+        for (int m = threadIdx.x; m < cs.ny; m += kRedThreads) {
+            x += acc_v[m];
+            y += acc_vc[m];
+        }
+    }
+    e = block_sum(e, lds);
+    x = block_sum(x, lds);
+    y = block_sum(y, lds);
+    if (threadIdx.x == 0) {
+        part[3 * n] = e;
+        part[3 * n + 1] = x;
+        part[3 * n + 2] = y;
+    }
+}
+
+__global__ __launch_bounds__(kRedThreads) void k_obs_final(int nx, int top_from,
+                                                           const double* part, double* out)
+{
+    __shared__ double lds[kRedThreads / kWave];
+    double tot = 0.0, top = 0.0;
+    for (int n = threadIdx.x; n < nx; n += kRedThreads) {
+        const double e = part[3 * n];
+        tot += e;
+        if (n >= top_from) top += e;
+    }
+    tot = block_sum(tot, lds);
+    top = block_sum(top, lds);
+    if (threadIdx.x == 0) {
+        out[0] = part[1];
+        out[1] = part[3 + 1];
+        out[2] = part[3 * nx + 1];
+        out[3] = part[3 * nx + 2];
+        out[4] = part[2];
+        out[5] = tot;
+        out[6] = top;
+    }
+}
 
 template <typename T>
-__global__ __launch_bounds__(kReduceThreads) void k_reduce_obs(Consts cs, const T* a_h,
-                                                               const T* b_h,
-                                                               const double* acc_v,
-                                                               const double* acc_vc, double* out)
+__global__ __launch_bounds__(kRedThreads) void k_check_stable(Consts cs, const T* a_h,
+                                                              const T* b_h, const Ctl* ctl,
+                                                              int* flag)
 {
-    __shared__ double sh[4][kReduceThreads];
-    double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
-    for (int m = threadIdx.x; m < cs.ny; m += kReduceThreads) {
-        s0 += static_cast<double>(a_h[m]);
-        s1 += static_cast<double>(b_h[cs.ld + m]);
-        s2 += acc_v[m];
-        s3 += acc_vc[m];
+    __shared__ double lds[kRedThreads / kWave];
+    double sa = 0.0, sb = 0.0;
+    for (int m = threadIdx.x; m < cs.ny; m += kRedThreads) {
+        sa += static_cast<double>(a_h[m]);
+        sb += static_cast<double>(b_h[cs.ld + m]);
     }
-    sh[0][threadIdx.x] = s0;
-    sh[1][threadIdx.x] = s1;
-    sh[2][threadIdx.x] = s2;
-    sh[3][threadIdx.x] = s3;
-    __syncthreads();
-    for (int w = kReduceThreads / 2; w > 0; w >>= 1) {
-        if (threadIdx.x < w) {
-            for (int q = 0; q < 4; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + w];
-        }
-        __syncthreads();
+    sa = block_sum(sa, lds);
+    sb = block_sum(sb, lds);
+    if (threadIdx.x == 0) {
+        const double ref = ctl->norm_ref;
+        const bool bad = !isfinite(sa) || !isfinite(sb) || !(fabs(sa - ref) <= 1e-2 * fabs(ref));
+        if (bad) __hip_atomic_store(flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     }
-    if (threadIdx.x < 4) out[threadIdx.x] = sh[threadIdx.x][0];
 }
 
 inline int round_up8(int x) { return (x + 7) & ~7; }
@@ -287,10 +365,23 @@ hipError_t launch_advance_counter(Ctl* ctl, int64_t n, hipStream_t st)
 
 template <typename T>
 hipError_t launch_reduce_obs(const Consts& cs, const T* a_h, const T* b_h, const double* acc_v,
-                             const double* acc_vc, double* out, hipStream_t st)
+                             const double* acc_vc, int edge_w, int top_from, double* part,
+                             double* out, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_reduce_obs<T>, dim3(1), dim3(kReduceThreads), 0, st, cs, a_h, b_h, acc_v,
-                       acc_vc, out);
+    hipLaunchKernelGGL(k_obs_rows<T>, dim3(cs.nx + 1), dim3(kRedThreads), 0, st, cs, a_h, b_h,
+                       acc_v, acc_vc, edge_w, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_obs_final, dim3(1), dim3(kRedThreads), 0, st, cs.nx, top_from, part, out);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_check_stable(const Consts& cs, const T* a_h, const T* b_h, const Ctl* ctl,
+                               int* flag, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_check_stable<T>, dim3(1), dim3(kRedThreads), 0, st, cs, a_h, b_h, ctl,
+                       flag);
     return hipGetLastError();
 }
 
@@ -311,7 +402,10 @@ hipError_t launch_reduce_obs(const Consts& cs, const T* a_h, const T* b_h, const
     template hipError_t launch_init_equilibrium<T>(const Consts&, T*, T*, const double*,        \
                                                    const double*, hipStream_t);                \
     template hipError_t launch_reduce_obs<T>(const Consts&, const T*, const T*, const double*,  \
-                                             const double*, double*, hipStream_t);
+                                             const double*, int, int, double*, double*,        \
+                                             hipStream_t);                                     \
+    template hipError_t launch_check_stable<T>(const Consts&, const T*, const T*, const Ctl*,   \
+                                               int*, hipStream_t);
 
 BTE_INSTANTIATE(double)
 BTE_INSTANTIATE(float)

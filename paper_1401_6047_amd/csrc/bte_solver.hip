@@ -91,7 +91,8 @@ struct Layout {
     int rows = 0;           // padded rows per plane
     size_t elem = 8;        // bytes per state element
     size_t plane_bytes = 0;
-    size_t off_ctl = 0, off_red = 0, off_s = 0, off_g = 0, off_accv = 0, off_accvc = 0;
+    size_t off_ctl = 0, off_red = 0, off_part = 0, off_s = 0, off_g = 0, off_accv = 0,
+           off_accvc = 0;
     size_t off_planes = 0;
     size_t total = 0;
 };
@@ -110,6 +111,7 @@ Layout make_layout(const bte_grid& g, int precision)
     size_t o = 0;
     L.off_ctl = o; o += align_up(sizeof(Ctl));
     L.off_red = o; o += align_up(8 * sizeof(double));
+    L.off_part = o; o += align_up(3 * sizeof(double) * (g.n_x + 1));
     L.off_s = o; o += align_up(sizeof(double) * g.n_x);
     L.off_g = o; o += align_up(sizeof(double) * g.n_y);
     L.off_accv = o; o += align_up(sizeof(double) * g.n_y);
@@ -176,7 +178,10 @@ struct bte_solver {
     int64_t acc_from = 0;           // accumulators count steps > acc_from
     double ratio1 = 0;              // I_1(mu)/I_0(mu)
     double norm0 = 0;               // normalisation of the initial state
+    double norm_ref = 0;            // sum_m a_0(m) of the initial state (device check)
     bool unstable = false;
+    int* flag_host = nullptr;       // sticky instability flag, written by the device
+    int* flag_dev = nullptr;        // its device address
     hipGraphExec_t graph[2] = {nullptr, nullptr};   // by starting set
     bool graph_flip[2] = {false, false};            // graph ends in the other set
     int graph_steps_built = -1;
@@ -184,6 +189,7 @@ struct bte_solver {
 
     bte::Ctl* ctl() { return reinterpret_cast<bte::Ctl*>(ws + L.off_ctl); }
     double* red() { return reinterpret_cast<double*>(ws + L.off_red); }
+    double* part() { return reinterpret_cast<double*>(ws + L.off_part); }
     double* s_n() { return reinterpret_cast<double*>(ws + L.off_s); }
     double* g_m() { return reinterpret_cast<double*>(ws + L.off_g); }
     double* acc_v() { return reinterpret_cast<double*>(ws + L.off_accv); }
@@ -291,7 +297,16 @@ hipError_t queue_steps_direct(bte_solver* s, int n, hipStream_t st)
         if (e != hipSuccess) return e;
         j += count;
     }
-    if (n > 0) return bte::launch_advance_counter(s->ctl(), n, st);
+    if (n > 0) {
+        hipError_t e = bte::launch_advance_counter(s->ctl(), n, st);
+        if (e != hipSuccess) return e;
+        return s->fp32() ? bte::launch_check_stable<float>(s->cs, s->plane<float>(s->cur, 0),
+                                                           s->plane<float>(s->cur, 1), s->ctl(),
+                                                           s->flag_dev, st)
+                         : bte::launch_check_stable<double>(s->cs, s->plane<double>(s->cur, 0),
+                                                            s->plane<double>(s->cur, 1), s->ctl(),
+                                                            s->flag_dev, st);
+    }
     return hipSuccess;
 }
 
@@ -349,6 +364,7 @@ bte_status write_ctl(bte_solver* s)
     c.k = s->step;
     c.win_lo = s->win_lo;
     c.win_hi = s->win_hi;
+    c.norm_ref = s->norm_ref;
     HIP_TRY(hipMemcpyAsync(s->ctl(), &c, sizeof(c), hipMemcpyHostToDevice, s->stream));
     HIP_TRY(hipStreamSynchronize(s->stream));
     return BTE_OK;
@@ -362,23 +378,30 @@ bte_status clear_acc(bte_solver* s)
     return BTE_OK;
 }
 
-// Reduce rows a_0, b_1 and the accumulators of the current set.
-bte_status reduce(bte_solver* s, double out[4])
+// phi_y points of each edge strip and first harmonic of the top of the
+// spectrum for the resolution diagnostics of bte_obs.
+int edge_width(int ny) { return std::max(1, (ny + 63) / 64); }
+int top_from(int nx) { return nx - std::max(1, nx / 8); }
+
+// Reduce the current set: out[0..6] as launch_reduce_obs documents.
+bte_status reduce(bte_solver* s, double out[bte::kObsOut])
 {
     const int set = s->cur;
+    const int ew = edge_width(s->grid.n_y), tf = top_from(s->grid.n_x);
     hipError_t e;
     if (s->fp32())
         e = bte::launch_reduce_obs<float>(s->cs, s->plane<float>(set, 0), s->plane<float>(set, 1),
-                                          s->acc_v(), s->acc_vc(), s->red(), s->stream);
+                                          s->acc_v(), s->acc_vc(), ew, tf, s->part(), s->red(),
+                                          s->stream);
     else
         e = bte::launch_reduce_obs<double>(s->cs, s->plane<double>(set, 0),
-                                           s->plane<double>(set, 1), s->acc_v(), s->acc_vc(),
-                                           s->red(), s->stream);
+                                           s->plane<double>(set, 1), s->acc_v(), s->acc_vc(), ew,
+                                           tf, s->part(), s->red(), s->stream);
     if (e != hipSuccess) return fail(BTE_EDEVICE, "reduction launch: %s", hipGetErrorString(e));
-    HIP_TRY(hipMemcpyAsync(s->pinned, s->red(), 4 * sizeof(double), hipMemcpyDeviceToHost,
-                           s->stream));
+    HIP_TRY(hipMemcpyAsync(s->pinned, s->red(), bte::kObsOut * sizeof(double),
+                           hipMemcpyDeviceToHost, s->stream));
     HIP_TRY(hipStreamSynchronize(s->stream));
-    std::memcpy(out, s->pinned, 4 * sizeof(double));
+    std::memcpy(out, s->pinned, bte::kObsOut * sizeof(double));
     return BTE_OK;
 }
 
@@ -416,13 +439,18 @@ bte_status copy_plane_in(bte_solver* s, int set, int which, const double* host, 
     return BTE_OK;
 }
 
+// Record the normalisation of the current state as the reference of the
+// stability checks (host: bte_observables; device: after every run of steps)
+// and clear the sticky flag.
 bte_status measure_norm0(bte_solver* s)
 {
-    double r[4];
+    double r[bte::kObsOut];
     bte_status st = reduce(s, r);
     if (st != BTE_OK) return st;
     s->norm0 = 2.0 * kPi * std::sqrt(s->params.alpha) * s->cs.dphi * r[0];
-    return BTE_OK;
+    s->norm_ref = r[0];
+    __atomic_store_n(s->flag_host, 0, __ATOMIC_SEQ_CST);
+    return write_ctl(s);
 }
 
 }  // namespace
@@ -472,9 +500,16 @@ bte_status bte_create(const bte_grid* grid, const bte_params* params, void* work
         s->owns_ws = true;
     }
     e = hipHostMalloc(reinterpret_cast<void**>(&s->pinned), 8 * sizeof(double), hipHostMallocDefault);
+    if (e == hipSuccess)
+        e = hipHostMalloc(reinterpret_cast<void**>(&s->flag_host), sizeof(int),
+                          hipHostMallocMapped | hipHostMallocCoherent);
+    if (e == hipSuccess) {
+        *s->flag_host = 0;
+        e = hipHostGetDevicePointer(reinterpret_cast<void**>(&s->flag_dev), s->flag_host, 0);
+    }
     if (e != hipSuccess) {
         bte_destroy(s);
-        return fail(BTE_ENOMEM, "hipHostMalloc: %s", hipGetErrorString(e));
+        return fail(BTE_ENOMEM, "pinned host buffers: %s", hipGetErrorString(e));
     }
 
     const double dphi = (grid->phiy_max - grid->phiy_min) / (grid->n_y - 1);
@@ -538,6 +573,9 @@ bte_status bte_step(bte_solver* s, int64_t n_steps)
 {
     if (!s) return fail(BTE_EINVAL, "solver is NULL");
     if (n_steps < 0) return fail(BTE_EINVAL, "n_steps must be >= 0");
+    // the device sets the flag when a run of steps ends with a non-finite or
+    // drifted norm or drift velocity; reading it costs no synchronisation
+    if (__atomic_load_n(s->flag_host, __ATOMIC_ACQUIRE) != 0) s->unstable = true;
     if (s->unstable) return fail(BTE_EUNSTABLE, "solver is flagged unstable; reset the state");
     int64_t left = n_steps;
     const int G = s->tune.graph_steps;
@@ -580,7 +618,7 @@ bte_status bte_set_window(bte_solver* s, int64_t lo, int64_t hi)
 bte_status bte_observables(bte_solver* s, bte_obs* out)
 {
     if (!s || !out) return fail(BTE_EINVAL, "solver and out must not be NULL");
-    double r[4];
+    double r[bte::kObsOut];
     bte_status st = reduce(s, r);
     if (st != BTE_OK) return st;
     const double f = kPi * std::sqrt(s->params.alpha) * s->cs.dphi;
@@ -592,6 +630,8 @@ bte_status bte_observables(bte_solver* s, bte_obs* out)
     out->n_avg = window_count(s);
     out->S_v = f * r[2];
     out->S_vc = f * r[3];
+    out->edge_mass = 2.0 * f * r[4];
+    out->top_harm_mass = r[5] > 0 ? r[6] / r[5] : 0.0;
     if (out->n_avg > 0) {
         const double K = static_cast<double>(out->n_avg);
         out->v_avg = out->S_v / K;
@@ -606,10 +646,59 @@ bte_status bte_observables(bte_solver* s, bte_obs* out)
     }
     const bool bad = !std::isfinite(out->norm) || !std::isfinite(out->v_dr) ||
                      !std::isfinite(out->S_v) || !std::isfinite(out->S_vc) ||
+                     !std::isfinite(r[5]) ||
                      std::fabs(out->norm - s->norm0) > 1e-2 * std::fabs(s->norm0);
-    if (bad) s->unstable = true;
+    if (bad || __atomic_load_n(s->flag_host, __ATOMIC_ACQUIRE) != 0) s->unstable = true;
     out->status = s->unstable ? BTE_EUNSTABLE : BTE_OK;
     return BTE_OK;
+}
+
+bte_status bte_run_periods(bte_solver* s, double tol, int32_t min_periods, int32_t max_periods,
+                           int32_t confirm, bte_result* out)
+{
+    if (!s || !out) return fail(BTE_EINVAL, "solver and out must not be NULL");
+    if (!(tol > 0) || !std::isfinite(tol)) return fail(BTE_EINVAL, "tol must be finite and > 0");
+    if (min_periods < 2 || max_periods < min_periods)
+        return fail(BTE_EINVAL, "need 2 <= min_periods <= max_periods");
+    if (confirm < 1) return fail(BTE_EINVAL, "confirm must be >= 1");
+    if (!(s->params.omega > 0)) return fail(BTE_EINVAL, "omega must be > 0 to define a period");
+    const double steps_per_period = 2.0 * kPi / (s->params.omega * s->params.dt);
+    if (!(steps_per_period < 4e18)) return fail(BTE_EINVAL, "period too long in steps");
+    const int64_t L = std::max<int64_t>(1, std::llround(steps_per_period));
+    std::memset(out, 0, sizeof(*out));
+    const int64_t k0 = s->step;
+    double A_prev = 0.0;
+    int run_ok = 0;
+    for (int p = 1;; ++p) {
+        const int64_t lo = k0 + static_cast<int64_t>(p - 1) * L, hi = lo + L;
+        bte_status st = bte_set_window(s, lo, hi);
+        if (st == BTE_OK) st = bte_step(s, L);
+        bte_obs o;
+        if (st == BTE_OK) st = bte_observables(s, &o);
+        if (st == BTE_EUNSTABLE) {
+            out->status = BTE_EUNSTABLE;
+            return BTE_OK;
+        }
+        if (st != BTE_OK) return st;
+        const double dA = p > 1 ? std::fabs(o.absorption_cov - A_prev) : 0.0;
+        out->absorption = o.absorption_cov;
+        out->v_avg = o.v_avg;
+        out->dA = dA;
+        out->steps = s->step - k0;
+        out->periods = p;
+        out->status = o.status;
+        if (o.status != BTE_OK || !std::isfinite(o.absorption_cov)) {
+            out->status = BTE_EUNSTABLE;
+            return BTE_OK;
+        }
+        run_ok = (p > 1 && dA < tol) ? run_ok + 1 : 0;
+        if (p >= min_periods && run_ok >= confirm) {
+            out->converged = 1;
+            return BTE_OK;
+        }
+        if (p >= max_periods) return BTE_OK;
+        A_prev = o.absorption_cov;
+    }
 }
 
 bte_status bte_get_state(bte_solver* s, double* a_h, double* b_h, double* a_f, double* b_f)
@@ -719,6 +808,7 @@ void bte_destroy(bte_solver* s)
     drop_graphs(s);
     if (s->capture_stream) (void)hipStreamDestroy(s->capture_stream);
     if (s->pinned) (void)hipHostFree(s->pinned);
+    if (s->flag_host) (void)hipHostFree(s->flag_host);
     if (s->owns_ws && s->ws) (void)hipFree(s->ws);
     delete s;
 }
