@@ -231,6 +231,34 @@ bte_status bte_reconstruct_coeffs(const double* a, const double* b, int32_t n_x,
                                   int64_t ld, int32_t n_phix, double* out, void* hip_stream);
 
 /* ------------------------------------------------------------------------ */
+/* Observables of a state the caller holds                                  */
+/* ------------------------------------------------------------------------ */
+/* Device bytes of scratch bte_state_observables needs for n_x harmonics
+   (partial sums, one row of three per harmonic plus a few).  BTE_EINVAL for
+   n_x outside 2..16384. */
+bte_status bte_state_observables_bytes(int32_t n_x, size_t* bytes);
+
+/* The Sec. 2 observables of a whole-grid state in caller device arrays a and
+   b (N_x rows of `ld` >= n_y doubles each; row n holds a_n or b_n at
+   m = 0 .. n_y-1; row 0 of b is not read), on the grid phi_y(m) = phiy_min +
+   m dphi, dphi = (phiy_max - phiy_min)/(n_y - 1):
+       out[0] = norm = 2 pi sqrt(alpha) dphi sum_m a_0(m)
+       out[1] = v_dr = pi sqrt(alpha) dphi sum_m b_1(m)
+       out[2] = edge_mass, out[3] = top_harm_mass (as in bte_obs).
+   `out` is a device array of 4 doubles.  The sums run in a fixed order (the
+   result does not depend on timing).  `workspace` is device scratch of at
+   least bte_state_observables_bytes(n_x) bytes, 256-byte aligned, that the
+   call overwrites; queued on `hip_stream` (a hipStream_t or NULL) with no
+   synchronisation.  A NULL workspace makes the call allocate and free one,
+   synchronising the stream before and after.  Errors: BTE_EINVAL for NULL or
+   misaligned pointers or bad sizes (n_y < 3, ld < n_y, alpha <= 0, phiy_max
+   <= phiy_min), BTE_ENOMEM for a short workspace. */
+bte_status bte_state_observables(const double* a, const double* b, int32_t n_x, int32_t n_y,
+                                 int64_t ld, double phiy_min, double phiy_max, double alpha,
+                                 void* workspace, size_t workspace_bytes, void* hip_stream,
+                                 double* out);
+
+/* ------------------------------------------------------------------------ */
 /* Batched parameter sweeps                                                  */
 /* ------------------------------------------------------------------------ */
 /* Many independent instances (each its own fields, temperature and phi_y

@@ -127,6 +127,10 @@ def _load():
         "bte_batch_results": ([vp, P(bte_result)], ctypes.c_int),
         "bte_batch_get_tuning": ([vp, P(bte_batch_tuning)], ctypes.c_int),
         "bte_batch_destroy": ([vp], None),
+        "bte_state_observables_bytes": ([ctypes.c_int32, P(ctypes.c_size_t)], ctypes.c_int),
+        "bte_state_observables": ([vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
+                                   ctypes.c_double, ctypes.c_double, ctypes.c_double, vp,
+                                   ctypes.c_size_t, vp, vp], ctypes.c_int),
         "bte_run_periods": ([vp, ctypes.c_double, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                              P(bte_result)], ctypes.c_int),
         "bte_destroy": ([vp], None),
@@ -331,6 +335,47 @@ def bte_run_periods(h: int, tol: float, min_periods: int, max_periods: int,
                                 int(max_periods), int(confirm), ctypes.byref(r)),
            "bte_run_periods")
     return r
+
+
+def bte_state_observables_bytes(n_x: int) -> int:
+    n = ctypes.c_size_t(0)
+    _check(_lib.bte_state_observables_bytes(int(n_x), ctypes.byref(n)),
+           "bte_state_observables_bytes")
+    return int(n.value)
+
+
+def bte_state_observables(a_ptr, b_ptr, n_x, n_y, ld, phiy_min, phiy_max, alpha, ws_ptr,
+                          ws_bytes, stream_ptr, out_ptr):
+    _check(_lib.bte_state_observables(ctypes.c_void_p(a_ptr or None), ctypes.c_void_p(b_ptr or None),
+                                      int(n_x), int(n_y), int(ld), float(phiy_min),
+                                      float(phiy_max), float(alpha), ctypes.c_void_p(ws_ptr or None),
+                                      int(ws_bytes), ctypes.c_void_p(stream_ptr or None),
+                                      ctypes.c_void_p(out_ptr or None)), "bte_state_observables")
+
+
+def state_observables(a, b, phiy_min, phiy_max, alpha=1.0, workspace=None, stream=None):
+    """(norm, v_dr, edge_mass, top_harm_mass) of FP64 CUDA coefficient tensors
+    a, b of shape (N_x, N_y) (rows may be strided; elements contiguous), as a
+    float64 CUDA tensor of 4.  `workspace`: a uint8 CUDA tensor of at least
+    bte_state_observables_bytes(N_x) + 256 bytes, or None to allocate one."""
+    import torch
+    for t in (a, b):
+        if t.dtype != torch.float64 or not t.is_cuda or t.dim() != 2 or t.stride(1) != 1:
+            raise ValueError("a and b must be 2-D float64 CUDA tensors with contiguous rows")
+    if a.shape != b.shape or a.stride(0) != b.stride(0):
+        raise ValueError("a and b must have the same shape and row stride")
+    nx, ny = a.shape
+    need = bte_state_observables_bytes(nx)
+    if workspace is None:
+        workspace = torch.empty(need + 256, dtype=torch.uint8, device=a.device)
+    ptr = (workspace.data_ptr() + 255) // 256 * 256
+    if ptr + need > workspace.data_ptr() + workspace.numel():
+        raise ValueError("workspace too small")
+    out = torch.empty(4, dtype=torch.float64, device=a.device)
+    st = stream if stream is not None else torch.cuda.current_stream(a.device)
+    bte_state_observables(a.data_ptr(), b.data_ptr(), nx, ny, a.stride(0), phiy_min, phiy_max,
+                          alpha, ptr, need, st.cuda_stream, out.data_ptr())
+    return out
 
 
 def bte_batch_destroy(h: int):

@@ -134,6 +134,13 @@ hipError_t launch_reduce_obs(const Consts& cs, const T* a_h, const T* b_h, const
                              const double* acc_vc, int edge_w, int top_from, double* part,
                              double* out, hipStream_t st);
 
+// launch_reduce_obs on caller arrays (no window sums), then out[0..3] =
+// (norm, v_dr, edge_mass, top_harm_mass) with f = pi sqrt(alpha) dphi.
+// `part` holds 3 * (nx + 1) doubles, `red` kObsOut.
+hipError_t launch_state_observables(const Consts& cs, const double* a, const double* b,
+                                   int edge_w, int top_from, double f, double* part,
+                                   double* red, double* out, hipStream_t st);
+
 // Stability check of the state after a run of steps: if sum_m a_0(m) or
 // sum_m b_1(m) is not finite, or sum_m a_0 differs from ctl->norm_ref by more
 // than 1e-2 of it, store 1 into *flag (host-visible memory, system scope).

@@ -201,6 +201,18 @@ __global__ __launch_bounds__(kRedThreads) void k_obs_final(int nx, int top_from,
     }
 }
 
+// Observables of a state from the reduction: out[0] = norm, out[1] = v_dr,
+// out[2] = edge_mass, out[3] = top_harm_mass; f = pi sqrt(alpha) dphi.
+__global__ void k_obs_finish(double f, const double* red, double* out)
+{
+    if (threadIdx.x == 0) {
+        out[0] = 2.0 * f * red[0];
+        out[1] = f * red[1];
+        out[2] = 2.0 * f * red[4];
+        out[3] = red[5] > 0.0 ? red[6] / red[5] : 0.0;
+    }
+}
+
 template <typename T>
 __global__ __launch_bounds__(kRedThreads) void k_check_stable(Consts cs, const T* a_h,
                                                               const T* b_h, const Ctl* ctl,
@@ -373,6 +385,17 @@ hipError_t launch_reduce_obs(const Consts& cs, const T* a_h, const T* b_h, const
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_obs_final, dim3(1), dim3(kRedThreads), 0, st, cs.nx, top_from, part, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_state_observables(const Consts& cs, const double* a, const double* b,
+                                   int edge_w, int top_from, double f, double* part,
+                                   double* red, double* out, hipStream_t st)
+{
+    hipError_t e = launch_reduce_obs<double>(cs, a, b, nullptr, nullptr, edge_w, top_from, part,
+                                             red, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_obs_finish, dim3(1), dim3(kWave), 0, st, f, red, out);
     return hipGetLastError();
 }
 

@@ -801,6 +801,63 @@ bte_status bte_reconstruct_coeffs(const double* a, const double* b, int32_t n_x,
     return BTE_OK;
 }
 
+bte_status bte_state_observables_bytes(int32_t n_x, size_t* bytes)
+{
+    if (!bytes) return fail(BTE_EINVAL, "bytes must not be NULL");
+    if (n_x < 2 || n_x > 16384) return fail(BTE_EINVAL, "n_x must be in 2..16384");
+    *bytes = align_up(3 * sizeof(double) * (n_x + 1)) + align_up(bte::kObsOut * sizeof(double));
+    return BTE_OK;
+}
+
+bte_status bte_state_observables(const double* a, const double* b, int32_t n_x, int32_t n_y,
+                                 int64_t ld, double phiy_min, double phiy_max, double alpha,
+                                 void* workspace, size_t workspace_bytes, void* hip_stream,
+                                 double* out)
+{
+    if (!a || !b || !out) return fail(BTE_EINVAL, "a, b and out must not be NULL");
+    const auto misaligned = [](const void* p) {
+        return reinterpret_cast<uintptr_t>(p) % alignof(double) != 0;
+    };
+    if (misaligned(a) || misaligned(b) || misaligned(out))
+        return fail(BTE_EINVAL, "a, b and out must be 8-byte aligned");
+    size_t need = 0;
+    bte_status st = bte_state_observables_bytes(n_x, &need);
+    if (st != BTE_OK) return st;
+    if (n_y < 3 || n_y > (1 << 24) || ld < n_y || ld > (int64_t(1) << 31))
+        return fail(BTE_EINVAL, "need 3 <= n_y <= 2^24 and n_y <= ld < 2^31");
+    if (!std::isfinite(phiy_min) || !std::isfinite(phiy_max) || !(phiy_max > phiy_min))
+        return fail(BTE_EINVAL, "need finite phiy_min < phiy_max");
+    if (!std::isfinite(alpha) || !(alpha > 0))
+        return fail(BTE_EINVAL, "alpha must be finite and > 0");
+    if (workspace && workspace_bytes < need)
+        return fail(BTE_ENOMEM, "workspace has %zu bytes, needs %zu", workspace_bytes, need);
+    if (workspace && reinterpret_cast<uintptr_t>(workspace) % kAlign != 0)
+        return fail(BTE_EINVAL, "workspace must be 256-byte aligned");
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    char* ws = static_cast<char*>(workspace);
+    if (!ws) {
+        HIP_TRY(hipStreamSynchronize(stream));
+        HIP_TRY(hipMalloc(reinterpret_cast<void**>(&ws), need));
+    }
+    bte::Consts cs{};
+    cs.nx = n_x;
+    cs.ny = n_y;
+    cs.ld = static_cast<int32_t>(ld);
+    const double dphi = (phiy_max - phiy_min) / (n_y - 1);
+    const double f = kPi * std::sqrt(alpha) * dphi;
+    double* part = reinterpret_cast<double*>(ws);
+    double* red = reinterpret_cast<double*>(ws + align_up(3 * sizeof(double) * (n_x + 1)));
+    hipError_t e = bte::launch_state_observables(cs, a, b, edge_width(n_y), top_from(n_x), f, part,
+                                                 red, out, stream);
+    if (!workspace) {
+        const hipError_t e2 = hipStreamSynchronize(stream);
+        (void)hipFree(ws);
+        if (e == hipSuccess) e = e2;
+    }
+    if (e != hipSuccess) return fail(BTE_EDEVICE, "state observables: %s", hipGetErrorString(e));
+    return BTE_OK;
+}
+
 void bte_destroy(bte_solver* s)
 {
     if (!s) return;

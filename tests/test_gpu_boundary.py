@@ -167,3 +167,52 @@ def test_run_periods_rejects_bad_arguments(bte):
             bte.bte_run_periods(s.handle, *args)
         assert ei.value.status == bte.BTE_EINVAL
     s.close()
+
+
+@pytest.mark.parametrize("nx,ny,pad", [(2, 3, 0), (17, 187, 5), (512, 8193, 71)])
+def test_state_observables_of_caller_arrays(bte, nx, ny, pad):
+    """bte_state_observables on strided caller arrays: norm, v_dr and the
+    resolution diagnostics of the Sec. 2 definitions, against the oracle's
+    formulas on the same values (and the same with the library allocating)."""
+    import torch
+    a, b = W.random_coeffs(nx * 3 + ny, nx, ny, decay=0.05)
+    b[0] = 0.0
+    ta = torch.zeros((nx, ny + pad), dtype=torch.float64, device="cuda")
+    tb = torch.zeros_like(ta)
+    ta[:, :ny] = torch.from_numpy(a)
+    tb[:, :ny] = torch.from_numpy(b)
+    lo, hi, alpha = -7.5, 7.5, 0.9496
+    got = bte.state_observables(ta[:, :ny], tb[:, :ny], lo, hi, alpha).cpu().numpy()
+    pb = oracle.Problem(nx=nx, ny=ny, phiy_min=lo, phiy_max=hi, E_dc=0, E_w=0, omega=1, B=0,
+                        mu=1, dt=1e-3, alpha=alpha)
+    dphi = (hi - lo) / (ny - 1)
+    f = math.pi * math.sqrt(alpha) * dphi
+    edge, top = oracle.resolution_diagnostics(pb, a, b)
+    want = [2 * f * a[0].sum(), f * b[1].sum(), edge, top]
+    scale = [2 * f * np.abs(a[0]).sum(), f * np.abs(b[1]).sum(), edge, top]
+    for g, w_, sc in zip(got, want, scale):
+        assert abs(g - w_) <= 1e-12 * sc
+    # the library-allocated workspace path gives the same bits
+    out = torch.empty(4, dtype=torch.float64, device="cuda")
+    bte.bte_state_observables(ta.data_ptr(), tb.data_ptr(), nx, ny, ta.stride(0), lo, hi, alpha,
+                              0, 0, torch.cuda.current_stream().cuda_stream, out.data_ptr())
+    assert (out.cpu().numpy() == got).all()
+
+
+def test_state_observables_rejects_bad_arguments(bte):
+    import torch
+    a = torch.zeros((4, 10), dtype=torch.float64, device="cuda")
+    out = torch.empty(4, dtype=torch.float64, device="cuda")
+    p = a.data_ptr()
+    bad = [(p, p, 1, 10, 10, -1, 1, 1), (p, p, 4, 2, 10, -1, 1, 1), (p, p, 4, 10, 9, -1, 1, 1),
+           (p, p, 4, 10, 10, 1, -1, 1), (p, p, 4, 10, 10, -1, 1, 0), (0, p, 4, 10, 10, -1, 1, 1)]
+    for args in bad:
+        with pytest.raises(bte.BteError) as ei:
+            bte.bte_state_observables(*args, 0, 0, 0, out.data_ptr())
+        assert ei.value.status == bte.BTE_EINVAL
+    need = bte.bte_state_observables_bytes(4)
+    ws = torch.empty(need + 512, dtype=torch.uint8, device="cuda")
+    wp = (ws.data_ptr() + 255) // 256 * 256
+    with pytest.raises(bte.BteError) as ei:
+        bte.bte_state_observables(p, p, 4, 10, 10, -1, 1, 1, wp, need - 8, 0, out.data_ptr())
+    assert ei.value.status == bte.BTE_ENOMEM
