@@ -71,6 +71,20 @@ struct Shape {
 };
 
 // ---- host helpers (bte_solver.hip) -----------------------------------------
+// Checked arguments of the state-observables entry points.
+struct StateObsArgs {
+    Consts cs;        // nx, ny, ld set; the rest zero
+    double f;         // pi sqrt(alpha) dphi
+    int edge_w;       // phi_y points per edge strip
+    int top_from;     // first harmonic of the top of the spectrum
+};
+// Validate (a, b, n_x, n_y, ld, box, alpha, out) as bte_state_observables
+// documents; sets bte_last_error and returns BTE_EINVAL on failure.
+int state_obs_validate(const double* a, const double* b, int32_t n_x, int32_t n_y, int64_t ld,
+                       double phiy_min, double phiy_max, double alpha, const double* out,
+                       StateObsArgs& v);
+// Byte offset of the reduction outputs after the partial sums of nx rows.
+size_t state_obs_red_offset(int nx);
 // Message returned by bte_last_error() on this thread.
 void set_last_error(const char* msg);
 // I_n(mu)/I_0(mu) for n = 0..nmax.

@@ -55,6 +55,11 @@ std::vector<double> bessel_ratio_table(double mu, int nmax)
     return out;
 }
 
+size_t state_obs_red_offset(int nx)
+{
+    return (3 * sizeof(double) * (nx + 1) + 255) / 256 * 256;
+}
+
 }  // namespace bte
 
 namespace {
@@ -382,6 +387,37 @@ bte_status clear_acc(bte_solver* s)
 // spectrum for the resolution diagnostics of bte_obs.
 int edge_width(int ny) { return std::max(1, (ny + 63) / 64); }
 int top_from(int nx) { return nx - std::max(1, nx / 8); }
+
+}  // namespace
+
+int bte::state_obs_validate(const double* a, const double* b, int32_t n_x, int32_t n_y,
+                            int64_t ld, double phiy_min, double phiy_max, double alpha,
+                            const double* out, StateObsArgs& v)
+{
+    if (!a || !b || !out) return fail(BTE_EINVAL, "a, b and out must not be NULL");
+    const auto misaligned = [](const void* p) {
+        return reinterpret_cast<uintptr_t>(p) % alignof(double) != 0;
+    };
+    if (misaligned(a) || misaligned(b) || misaligned(out))
+        return fail(BTE_EINVAL, "a, b and out must be 8-byte aligned");
+    if (n_x < 2 || n_x > 16384) return fail(BTE_EINVAL, "n_x must be in 2..16384");
+    if (n_y < 3 || n_y > (1 << 24) || ld < n_y || ld > (int64_t(1) << 31) - 1)
+        return fail(BTE_EINVAL, "need 3 <= n_y <= 2^24 and n_y <= ld < 2^31");
+    if (!std::isfinite(phiy_min) || !std::isfinite(phiy_max) || !(phiy_max > phiy_min))
+        return fail(BTE_EINVAL, "need finite phiy_min < phiy_max");
+    if (!std::isfinite(alpha) || !(alpha > 0))
+        return fail(BTE_EINVAL, "alpha must be finite and > 0");
+    v.cs = bte::Consts{};
+    v.cs.nx = n_x;
+    v.cs.ny = n_y;
+    v.cs.ld = static_cast<int32_t>(ld);
+    v.f = kPi * std::sqrt(alpha) * ((phiy_max - phiy_min) / (n_y - 1));
+    v.edge_w = edge_width(n_y);
+    v.top_from = top_from(n_x);
+    return BTE_OK;
+}
+
+namespace {
 
 // Reduce the current set: out[0..6] as launch_reduce_obs documents.
 bte_status reduce(bte_solver* s, double out[bte::kObsOut])
@@ -805,7 +841,7 @@ bte_status bte_state_observables_bytes(int32_t n_x, size_t* bytes)
 {
     if (!bytes) return fail(BTE_EINVAL, "bytes must not be NULL");
     if (n_x < 2 || n_x > 16384) return fail(BTE_EINVAL, "n_x must be in 2..16384");
-    *bytes = align_up(3 * sizeof(double) * (n_x + 1)) + align_up(bte::kObsOut * sizeof(double));
+    *bytes = bte::state_obs_red_offset(n_x) + align_up(bte::kObsOut * sizeof(double));
     return BTE_OK;
 }
 
@@ -814,21 +850,13 @@ bte_status bte_state_observables(const double* a, const double* b, int32_t n_x, 
                                  void* workspace, size_t workspace_bytes, void* hip_stream,
                                  double* out)
 {
-    if (!a || !b || !out) return fail(BTE_EINVAL, "a, b and out must not be NULL");
-    const auto misaligned = [](const void* p) {
-        return reinterpret_cast<uintptr_t>(p) % alignof(double) != 0;
-    };
-    if (misaligned(a) || misaligned(b) || misaligned(out))
-        return fail(BTE_EINVAL, "a, b and out must be 8-byte aligned");
-    size_t need = 0;
-    bte_status st = bte_state_observables_bytes(n_x, &need);
+    bte::StateObsArgs v;
+    bte_status st = static_cast<bte_status>(
+        bte::state_obs_validate(a, b, n_x, n_y, ld, phiy_min, phiy_max, alpha, out, v));
     if (st != BTE_OK) return st;
-    if (n_y < 3 || n_y > (1 << 24) || ld < n_y || ld > (int64_t(1) << 31))
-        return fail(BTE_EINVAL, "need 3 <= n_y <= 2^24 and n_y <= ld < 2^31");
-    if (!std::isfinite(phiy_min) || !std::isfinite(phiy_max) || !(phiy_max > phiy_min))
-        return fail(BTE_EINVAL, "need finite phiy_min < phiy_max");
-    if (!std::isfinite(alpha) || !(alpha > 0))
-        return fail(BTE_EINVAL, "alpha must be finite and > 0");
+    size_t need = 0;
+    st = bte_state_observables_bytes(n_x, &need);
+    if (st != BTE_OK) return st;
     if (workspace && workspace_bytes < need)
         return fail(BTE_ENOMEM, "workspace has %zu bytes, needs %zu", workspace_bytes, need);
     if (workspace && reinterpret_cast<uintptr_t>(workspace) % kAlign != 0)
@@ -839,16 +867,10 @@ bte_status bte_state_observables(const double* a, const double* b, int32_t n_x, 
         HIP_TRY(hipStreamSynchronize(stream));
         HIP_TRY(hipMalloc(reinterpret_cast<void**>(&ws), need));
     }
-    bte::Consts cs{};
-    cs.nx = n_x;
-    cs.ny = n_y;
-    cs.ld = static_cast<int32_t>(ld);
-    const double dphi = (phiy_max - phiy_min) / (n_y - 1);
-    const double f = kPi * std::sqrt(alpha) * dphi;
     double* part = reinterpret_cast<double*>(ws);
-    double* red = reinterpret_cast<double*>(ws + align_up(3 * sizeof(double) * (n_x + 1)));
-    hipError_t e = bte::launch_state_observables(cs, a, b, edge_width(n_y), top_from(n_x), f, part,
-                                                 red, out, stream);
+    double* red = reinterpret_cast<double*>(ws + bte::state_obs_red_offset(n_x));
+    hipError_t e = bte::launch_state_observables(v.cs, a, b, v.edge_w, v.top_from, v.f, part, red,
+                                                 out, stream);
     if (!workspace) {
         const hipError_t e2 = hipStreamSynchronize(stream);
         (void)hipFree(ws);
