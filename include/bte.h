@@ -155,9 +155,12 @@ bte_status bte_create(const bte_grid* grid, const bte_params* params, void* work
    per-phi_y accumulators.  Queues work only.
    Stability: after every captured run of steps (each graph replay) and every
    run of direct launches, the device checks the state's norm and drift
-   velocity and, when either is not finite or the norm has drifted by more
-   than 1e-2 of its initial value (the norm-deviation bound reported in the
-   paper's Sec. 4), sets a sticky flag in host-visible memory.  Every later
+   velocity and, when either is not finite or the norm lies further from
+   its equilibrium value (that of f0) than the initial state's norm did by
+   more than 1e-2 of it (the norm-deviation bound reported in the paper's
+   Sec. 4; relaxation alone moves the norm monotonically toward f0's, so a
+   resolved run never exceeds this), sets a sticky flag in host-visible
+   memory.  Every later
    bte_step reads that flag without synchronising and returns BTE_EUNSTABLE,
    queueing nothing, once the device has set it; bte_set_state clears it. */
 bte_status bte_step(bte_solver* s, int64_t n_steps);
@@ -168,8 +171,9 @@ bte_status bte_set_window(bte_solver* s, int64_t lo, int64_t hi);
 
 /* Reduce and return the observables of the current state (synchronises).
    Flags the handle unstable (status BTE_EUNSTABLE, sticky) when an
-   observable or the state's f^2 integral is not finite or the norm has
-   drifted by more than 1e-2 of its initial value. */
+   observable or the state's f^2 integral is not finite or the norm lies
+   further from f0's norm than the initial state's did by more than 1e-2 of
+   f0's norm. */
 bte_status bte_observables(bte_solver* s, bte_obs* out);
 
 /* Copy the state out as four [N_x][N_y] FP64 host arrays (whole grid a, b at

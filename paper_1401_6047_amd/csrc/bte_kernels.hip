@@ -227,8 +227,9 @@ __global__ __launch_bounds__(kRedThreads) void k_check_stable(Consts cs, const T
     sa = block_sum(sa, lds);
     sb = block_sum(sb, lds);
     if (threadIdx.x == 0) {
-        const double ref = ctl->norm_ref;
-        const bool bad = !isfinite(sa) || !isfinite(sb) || !(fabs(sa - ref) <= 1e-2 * fabs(ref));
+        const double eq = ctl->norm_eq;
+        const double allowed = fabs(ctl->norm_ref - eq) + 1e-2 * fabs(eq);
+        const bool bad = !isfinite(sa) || !isfinite(sb) || !(fabs(sa - eq) <= allowed);
         if (bad) __hip_atomic_store(flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     }
 }

@@ -184,6 +184,7 @@ struct bte_solver {
     double ratio1 = 0;              // I_1(mu)/I_0(mu)
     double norm0 = 0;               // normalisation of the initial state
     double norm_ref = 0;            // sum_m a_0(m) of the initial state (device check)
+    double norm_eq = 0;             // sum_m a0_{0,m}: the value sum_m a_0 relaxes to
     bool unstable = false;
     int* flag_host = nullptr;       // sticky instability flag, written by the device
     int* flag_dev = nullptr;        // its device address
@@ -370,6 +371,7 @@ bte_status write_ctl(bte_solver* s)
     c.win_lo = s->win_lo;
     c.win_hi = s->win_hi;
     c.norm_ref = s->norm_ref;
+    c.norm_eq = s->norm_eq;
     HIP_TRY(hipMemcpyAsync(s->ctl(), &c, sizeof(c), hipMemcpyHostToDevice, s->stream));
     HIP_TRY(hipStreamSynchronize(s->stream));
     return BTE_OK;
@@ -573,10 +575,13 @@ bte_status bte_create(const bte_grid* grid, const bte_params* params, void* work
     std::vector<double> sn(grid->n_x), gm(grid->n_y);
     const double norm = std::sqrt(params->mu / (2.0 * kPi * params->alpha)) / kPi;
     for (int n = 0; n < grid->n_x; ++n) sn[n] = (n == 0 ? 0.5 : 1.0) * ratio[n] * norm;
+    double gsum = 0.0;
     for (int m = 0; m < grid->n_y; ++m) {
         const double phi = grid->phiy_min + m * dphi;
         gm[m] = std::exp(-0.5 * params->mu * phi * phi);
+        gsum += gm[m];
     }
+    s->norm_eq = sn[0] * gsum;
 
     auto bail = [&](bte_status code) {
         std::string msg = g_last_error;
@@ -680,10 +685,13 @@ bte_status bte_observables(bte_solver* s, bte_obs* out)
         out->S_c = sc;
         out->absorption_cov = (2.0 / s->ratio1) * (out->S_vc - out->v_avg * sc) / K;
     }
+    // the normalisation relaxes from its initial value toward the equilibrium
+    // one; it must not move further away than it started (plus 1e-2 of it)
+    const double eq = 2.0 * f * s->norm_eq;
     const bool bad = !std::isfinite(out->norm) || !std::isfinite(out->v_dr) ||
                      !std::isfinite(out->S_v) || !std::isfinite(out->S_vc) ||
                      !std::isfinite(r[5]) ||
-                     std::fabs(out->norm - s->norm0) > 1e-2 * std::fabs(s->norm0);
+                     !(std::fabs(out->norm - eq) <= std::fabs(s->norm0 - eq) + 1e-2 * std::fabs(eq));
     if (bad || __atomic_load_n(s->flag_host, __ATOMIC_ACQUIRE) != 0) s->unstable = true;
     out->status = s->unstable ? BTE_EUNSTABLE : BTE_OK;
     return BTE_OK;
