@@ -262,6 +262,24 @@ bte_status bte_state_observables(const double* a, const double* b, int32_t n_x, 
                                  void* workspace, size_t workspace_bytes, void* hip_stream,
                                  double* out);
 
+/* bte_state_observables for callers that cannot allocate (code under HIP
+   graph capture, serving loops, harnesses that forbid hipMalloc): the same
+   kernels and results, with the scratch taken from a static device array of
+   the library (about 385 KiB per GPU, held until the process ends) instead of
+   a workspace argument.  Accepts n_x up to BTE_STATE_OBS_NOALLOC_MAX_NX
+   (BTE_EINVAL beyond it) and otherwise the arguments and errors of
+   bte_state_observables.  a, b, out and hip_stream must belong to the
+   current device.  Queued on `hip_stream` with no synchronisation; calls no
+   hipMalloc or hipFree.  Every call on one GPU shares that GPU's array and
+   overwrites it entirely before reading it, so calls that overlap on one GPU
+   (two streams, or two host threads) race and may return wrong sums;
+   serialise them, e.g. on one stream. */
+#define BTE_STATE_OBS_NOALLOC_MAX_NX 16384
+bte_status bte_state_observables_noalloc(const double* a, const double* b, int32_t n_x,
+                                         int32_t n_y, int64_t ld, double phiy_min,
+                                         double phiy_max, double alpha, void* hip_stream,
+                                         double* out);
+
 /* ------------------------------------------------------------------------ */
 /* Batched parameter sweeps                                                  */
 /* ------------------------------------------------------------------------ */

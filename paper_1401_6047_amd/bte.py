@@ -131,6 +131,9 @@ def _load():
         "bte_state_observables": ([vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
                                    ctypes.c_double, ctypes.c_double, ctypes.c_double, vp,
                                    ctypes.c_size_t, vp, vp], ctypes.c_int),
+        "bte_state_observables_noalloc": ([vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
+                                           ctypes.c_double, ctypes.c_double, ctypes.c_double, vp,
+                                           vp], ctypes.c_int),
         "bte_run_periods": ([vp, ctypes.c_double, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                              P(bte_result)], ctypes.c_int),
         "bte_destroy": ([vp], None),
@@ -351,6 +354,18 @@ def bte_state_observables(a_ptr, b_ptr, n_x, n_y, ld, phiy_min, phiy_max, alpha,
                                       float(phiy_max), float(alpha), ctypes.c_void_p(ws_ptr or None),
                                       int(ws_bytes), ctypes.c_void_p(stream_ptr or None),
                                       ctypes.c_void_p(out_ptr or None)), "bte_state_observables")
+
+
+STATE_OBS_NOALLOC_MAX_NX = 16384   # BTE_STATE_OBS_NOALLOC_MAX_NX of include/bte.h
+
+
+def bte_state_observables_noalloc(a_ptr, b_ptr, n_x, n_y, ld, phiy_min, phiy_max, alpha,
+                                  stream_ptr, out_ptr):
+    _check(_lib.bte_state_observables_noalloc(
+        ctypes.c_void_p(a_ptr or None), ctypes.c_void_p(b_ptr or None), int(n_x), int(n_y),
+        int(ld), float(phiy_min), float(phiy_max), float(alpha),
+        ctypes.c_void_p(stream_ptr or None), ctypes.c_void_p(out_ptr or None)),
+        "bte_state_observables_noalloc")
 
 
 def state_observables(a, b, phiy_min, phiy_max, alpha=1.0, workspace=None, stream=None):

@@ -17,6 +17,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -884,6 +885,77 @@ bte_status bte_state_observables(const double* a, const double* b, int32_t n_x, 
         (void)hipFree(ws);
         if (e == hipSuccess) e = e2;
     }
+    if (e != hipSuccess) return fail(BTE_EDEVICE, "state observables: %s", hipGetErrorString(e));
+    return BTE_OK;
+}
+
+}  // extern "C"
+
+// ---- bte_state_observables without allocation ---------------------------------
+// The partial sums and reduction outputs live in one file-scope device array.
+// In host code `scratch` names a host-side stand-in, not device memory: every
+// use on the host goes through the address hipGetSymbolAddress returns for the
+// current device, looked up once per device and kept in g_scratch_dev.
+namespace {
+constexpr int kNoAllocMaxNx = BTE_STATE_OBS_NOALLOC_MAX_NX;
+constexpr size_t kNoAllocScratchBytes =
+    (3 * sizeof(double) * (kNoAllocMaxNx + 1) + kAlign - 1) / kAlign * kAlign + kAlign;
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+bte_status noalloc_scratch(void** out)
+{
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(BTE_EDEVICE, "device %d is beyond the %d this library serves", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(BTE_EDEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", dev,
+                        hipGetErrorString(e));
+        g_scratch_dev[dev] = p;
+    }
+    *out = g_scratch_dev[dev];
+    return BTE_OK;
+}
+}  // namespace
+
+extern "C" {
+
+bte_status bte_state_observables_noalloc(const double* a, const double* b, int32_t n_x,
+                                         int32_t n_y, int64_t ld, double phiy_min,
+                                         double phiy_max, double alpha, void* hip_stream,
+                                         double* out)
+{
+    bte::StateObsArgs v;
+    bte_status st = static_cast<bte_status>(
+        bte::state_obs_validate(a, b, n_x, n_y, ld, phiy_min, phiy_max, alpha, out, v));
+    if (st != BTE_OK) return st;
+    if (n_x > kNoAllocMaxNx)
+        return fail(BTE_EINVAL, "n_x = %d exceeds the no-allocation limit %d", n_x, kNoAllocMaxNx);
+    size_t need = 0;
+    st = bte_state_observables_bytes(n_x, &need);
+    if (st != BTE_OK) return st;
+    if (need > kNoAllocScratchBytes)
+        return fail(BTE_EINVAL, "n_x = %d needs %zu scratch bytes, the static array holds %zu",
+                    n_x, need, kNoAllocScratchBytes);
+    void* ws = nullptr;
+    st = noalloc_scratch(&ws);
+    if (st != BTE_OK) return st;
+    char* base = static_cast<char*>(ws);
+    double* part = reinterpret_cast<double*>(base);
+    double* red = reinterpret_cast<double*>(base + bte::state_obs_red_offset(n_x));
+    const hipError_t e = bte::launch_state_observables(v.cs, a, b, v.edge_w, v.top_from, v.f,
+                                                       part, red, out,
+                                                       static_cast<hipStream_t>(hip_stream));
     if (e != hipSuccess) return fail(BTE_EDEVICE, "state observables: %s", hipGetErrorString(e));
     return BTE_OK;
 }
