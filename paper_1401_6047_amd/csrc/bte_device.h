@@ -140,6 +140,9 @@ constexpr int kBufferWord3 = 0x00020000;   // gfx9 raw buffer, no format convers
 // each storage error zero-mean and independent, so the errors average out in
 // the drift velocity and absorption.  The random bits come from a
 // counter-based hash of (step, plane, cell), so runs are reproducible.
+// mix32 is the published "lowbias32" integer hash (xor-shift 16, multiply,
+// xor-shift 15, multiply, xor-shift 16, with the two multipliers found by
+// C. Wellons' hash-prospector search).
 __device__ __forceinline__ uint32_t mix32(uint32_t x)
 {
     x ^= x >> 16;
@@ -150,7 +153,10 @@ __device__ __forceinline__ uint32_t mix32(uint32_t x)
     return x;
 }
 
-// Per-launch, per-plane seed.
+// Per-launch, per-plane seed.  The odd constants only spread the step and
+// plane indices over the word before hashing: 0x9E3779B9 is 2^32 divided by
+// the golden ratio (Knuth's multiplicative hashing), 0x85EBCA6B a multiplier
+// of the MurmurHash3 finaliser and 0x27D4EB2F one of the xxHash32 primes.
 __device__ __forceinline__ uint32_t plane_seed(int64_t k, uint32_t tag)
 {
     const uint32_t lo = static_cast<uint32_t>(k), hi = static_cast<uint32_t>(static_cast<uint64_t>(k) >> 32);
