@@ -414,6 +414,23 @@ bte_status bte_batch_get_tuning(const bte_batch* b, bte_batch_tuning* t);
 
 void bte_batch_destroy(bte_batch* b);
 
+/* Sweep autotuner: pick the batch's tile (kernel form FUSED2 or FUSED,
+   harmonics per wave among the values that split n_x into 1 to 8 equal
+   chunks, wavefronts per group 2, 4 or 8; wide schedule) by measurement.
+   The cost per step of an instance depends only on its grid, so the tuner
+   runs a sample of up to 128 instances whose N_y values follow the batch's
+   share of cells, each with omega raised to periods of 400 steps and run for exactly
+   two periods (a fixed amount of work), once per candidate (after one
+   untimed run that captures the graphs), on `hip_stream`.  The library
+   allocates and frees the sample's device memory itself (a few GiB at most
+   for the largest grids).  With use_cache != 0 an earlier result for the same
+   (n_x, set of N_y values, precision) in this process is returned without
+   measuring.  *out receives the tuning; *cell_steps_per_s (may be NULL) the
+   sample's rate in cell-steps per second.  Errors as bte_batch_create. */
+bte_status bte_batch_tune(const bte_batch_config* cfg, int32_t n, const bte_instance* inst,
+                          void* hip_stream, int32_t use_cache, bte_batch_tuning* out,
+                          double* cell_steps_per_s);
+
 /* The sweep's stopping rule on one solver: run whole ac periods of
    L = round(2 pi / (omega dt)) steps from the current step k0 (period p
    covers k0 + (p-1) L < k <= k0 + p L; k0 = 0 starts at phase 0 of the

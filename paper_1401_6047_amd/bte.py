@@ -127,6 +127,8 @@ def _load():
         "bte_batch_results": ([vp, P(bte_result)], ctypes.c_int),
         "bte_batch_get_tuning": ([vp, P(bte_batch_tuning)], ctypes.c_int),
         "bte_batch_destroy": ([vp], None),
+        "bte_batch_tune": ([P(bte_batch_config), ctypes.c_int32, P(bte_instance), vp, ctypes.c_int32,
+                            P(bte_batch_tuning), dp], ctypes.c_int),
         "bte_state_observables_bytes": ([ctypes.c_int32, P(ctypes.c_size_t)], ctypes.c_int),
         "bte_state_observables": ([vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
                                    ctypes.c_double, ctypes.c_double, ctypes.c_double, vp,
@@ -531,19 +533,37 @@ def make_batch_config(n_x, phiy_min, phiy_max, dt, precision=BTE_FP64, alpha=1.0
                             int(max_periods), int(confirm), 0)
 
 
+def bte_batch_tune(cfg: bte_batch_config, instances, stream_ptr=0, use_cache=True):
+    """(tuning, sample cell-steps/s) from the library's sweep autotuner."""
+    arr = _inst_array(instances)
+    t = bte_batch_tuning()
+    rate = ctypes.c_double(0.0)
+    _check(_lib.bte_batch_tune(ctypes.byref(cfg), len(arr), arr, ctypes.c_void_p(stream_ptr or None),
+                               1 if use_cache else 0, ctypes.byref(t), ctypes.byref(rate)),
+           "bte_batch_tune")
+    return t, rate.value
+
+
+def tuning_cache_key(cfg: bte_batch_config, instances) -> str:
+    """Key of a batch tuning: harmonics, precision and the set of N_y values."""
+    nys = sorted({int(w.ny) for w in instances})
+    return f"nx{cfg.n_x}-p{cfg.precision}-ny" + ",".join(str(v) for v in nys)
+
+
 class Batch:
     """A batched sweep of independent instances (see bte_batch_* in bte.h).
 
     `instances` are objects with E_dc, E_w, omega, B, mu, ny (e.g. Workload).
     With `tuning=None`: the two-step kernel, 58 harmonics per wave, 4
     wavefronts per group, and the wide schedule unless its per-instance slots
-    would pass 64 GiB.  `autotune=True` takes the kernel form and harmonics
-    per wave from the single-instance tuner on the largest instance's grid
-    instead (which tunes for one instance filling the GPU, and so picks
-    shapes that are slower in a batch)."""
+    would pass 64 GiB.  `autotune=True` takes the tile from the library's
+    sweep autotuner (bte_batch_tune: a sample of this batch timed per
+    candidate shape); `tuning_cache` names a JSON file that keeps its results
+    across processes, keyed by (N_x, precision, set of N_y values)."""
 
     def __init__(self, cfg: bte_batch_config, instances, tuning=None, waves_per_group=4,
-                 groups=0, device="cuda", stream=None, autotune=False, schedule=None):
+                 groups=0, device="cuda", stream=None, autotune=False, schedule=None,
+                 tuning_cache=None):
         import torch
         self.cfg = cfg
         self.instances = list(instances)
@@ -557,25 +577,11 @@ class Batch:
             elem = 4 if cfg.precision == BTE_FP32_BULK else 8
             slot = 8 * (cfg.n_x + 8) * (ny + 128) * elem
             schedule = BTE_BATCH_WIDE if slot * self.n <= 64 * 2 ** 30 else BTE_BATCH_PERSISTENT
+        self.tune_rate = None
+        if tuning is None and autotune and schedule == BTE_BATCH_WIDE:
+            tuning = self._autotune(cfg, tuning_cache)
         if tuning is None:
             tuning = bte_batch_tuning(BTE_KERNEL_FUSED2, 58, waves_per_group, groups, schedule)
-            if autotune:
-                big = max(self.instances, key=lambda w: w.ny)
-                g = make_grid(cfg.n_x, big.ny, cfg.phiy_min, cfg.phiy_max)
-                p = make_params(big.E_dc, big.E_w, big.omega, big.B, big.mu, cfg.dt,
-                                alpha=cfg.alpha, precision=cfg.precision)
-                nbytes = bte_workspace_bytes(g, p)
-                scratch = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
-                ptr = (scratch.data_ptr() + 255) // 256 * 256
-                best = None
-                for form in (BTE_KERNEL_FUSED, BTE_KERNEL_FUSED2):
-                    t, us = bte_tune(g, p, ptr, nbytes, self.stream.cuda_stream, form, 1.0)
-                    if best is None or us < best[1]:
-                        best = (t, us)
-                del scratch
-                tuning.kernel = best[0].kernel
-                tuning.rows_per_wave = best[0].rows_per_wave
-                self.tune_us = best[1]
         self.tuning = tuning
         nbytes = bte_batch_workspace_bytes(cfg, self.instances, tuning)
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
@@ -583,6 +589,27 @@ class Batch:
         self.handle = bte_batch_create(cfg, self.instances, tuning, ptr, nbytes,
                                        self.stream.cuda_stream)
         self._warm = None
+
+    def _autotune(self, cfg, cache_path):
+        import json
+        key = tuning_cache_key(cfg, self.instances)
+        table = {}
+        if cache_path and os.path.exists(cache_path):
+            with open(cache_path) as f:
+                table = json.load(f)
+        if key in table:
+            e = table[key]
+            self.tune_rate = e.get("cell_steps_per_s")
+            return bte_batch_tuning(e["kernel"], e["rows_per_wave"], e["waves_per_group"], 0,
+                                    BTE_BATCH_WIDE)
+        t, rate = bte_batch_tune(cfg, self.instances, self.stream.cuda_stream)
+        self.tune_rate = rate
+        if cache_path:
+            table[key] = {"kernel": t.kernel, "rows_per_wave": t.rows_per_wave,
+                          "waves_per_group": t.waves_per_group, "cell_steps_per_s": rate}
+            with open(cache_path, "w") as f:
+                json.dump(table, f, indent=1, sort_keys=True)
+        return t
 
     def set_warm_start(self, coeffs):
         """coeffs: a contiguous float32 CUDA tensor of shape (n, 64, 128), or None."""

@@ -15,8 +15,11 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -1154,6 +1157,137 @@ bte_status bte_batch_get_tuning(const bte_batch* b, bte_batch_tuning* t)
     if (!b || !t) return bfail(BTE_EINVAL, "batch and tuning must not be NULL");
     *t = b->tune;
     t->groups = b->L.groups;
+    return BTE_OK;
+}
+
+}  // extern "C"
+
+// ---- sweep autotuner ------------------------------------------------------------
+// The per-step cost of an instance depends only on its grid (N_x shared, its
+// own N_y) and the tile shape, not on its fields: the tuner runs a sample of
+// the batch whose N_y values follow the batch's share of cells, with omega
+// raised so that every instance runs exactly `kTunePeriods` periods of
+// `kTunePeriodSteps` steps (a fixed, known amount of work), through the wide
+// schedule, and times it for each candidate shape.
+namespace {
+constexpr int kTuneSample = 128;        // instances in the tuning sample (at most)
+constexpr int kTunePeriodSteps = 400;   // steps per period of a sample instance
+constexpr int kTunePeriods = 2;
+
+struct TuneKey {
+    int n_x, precision;
+    std::vector<int> ny;                // distinct N_y values of the batch, sorted
+    bool operator<(const TuneKey& o) const
+    {
+        if (n_x != o.n_x) return n_x < o.n_x;
+        if (precision != o.precision) return precision < o.precision;
+        return ny < o.ny;
+    }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, std::pair<bte_batch_tuning, double>> g_tune_cache;
+
+// Harmonics per wave that split N_x into c equal chunks (c = 1 .. 8), up to
+// the form's limit.
+std::vector<int> balanced_rows(int nx, int rmax)
+{
+    std::vector<int> r;
+    for (int c = 1; c <= 8; ++c) {
+        const int R = (nx + c - 1) / c;
+        if (R <= rmax && (r.empty() || r.back() != R)) r.push_back(R);
+    }
+    return r;
+}
+}  // namespace
+
+extern "C" {
+
+bte_status bte_batch_tune(const bte_batch_config* cfg, int32_t n, const bte_instance* inst,
+                          void* hip_stream, int32_t use_cache, bte_batch_tuning* out,
+                          double* cell_steps_per_s)
+{
+    if (!out) return bfail(BTE_EINVAL, "out must not be NULL");
+    int ny_max = 0;
+    bte_status st = validate_batch(cfg, n, inst, nullptr, &ny_max);
+    if (st != BTE_OK) return st;
+    // cells per distinct N_y, and the cache key
+    std::map<int, double> cells;
+    for (int i = 0; i < n; ++i) cells[inst[i].n_y] += static_cast<double>(inst[i].n_y) * cfg->n_x;
+    TuneKey key{cfg->n_x, cfg->precision, {}};
+    for (const auto& kv : cells) key.ny.push_back(kv.first);
+    if (use_cache) {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            *out = it->second.first;
+            if (cell_steps_per_s) *cell_steps_per_s = it->second.second;
+            return BTE_OK;
+        }
+    }
+    // the sample: N_y classes in proportion to their cells, at least one each
+    double total = 0.0;
+    for (const auto& kv : cells) total += kv.second;
+    const int m = std::min<int>(n, kTuneSample);
+    std::vector<bte_instance> sample;
+    for (const auto& kv : cells) {
+        const int k = std::max(1, static_cast<int>(std::lround(m * kv.second / total)));
+        // a representative instance of the class (its fields do not change
+        // the cost), with omega set for periods of kTunePeriodSteps steps
+        const bte_instance* rep = nullptr;
+        for (int i = 0; i < n && !rep; ++i)
+            if (inst[i].n_y == kv.first) rep = &inst[i];
+        bte_instance x = *rep;
+        x.omega = 2.0 * kPi / (kTunePeriodSteps * cfg->dt);
+        for (int j = 0; j < k; ++j) sample.push_back(x);
+    }
+    bte_batch_config c = *cfg;
+    c.min_periods = c.max_periods = kTunePeriods;
+    c.confirm = 1;
+    double work = 0.0;
+    for (const bte_instance& x : sample)
+        work += static_cast<double>(x.n_y) * c.n_x * kTunePeriods * kTunePeriodSteps;
+
+    std::vector<bte_batch_tuning> cand;
+    for (int form : {BTE_KERNEL_FUSED2, BTE_KERNEL_FUSED})
+        for (int R : balanced_rows(c.n_x, form == BTE_KERNEL_FUSED2 ? 58 : bte::kWave - 2))
+            for (int w : {2, 4, 8}) {
+                bte_batch_tuning t{};
+                t.kernel = form;
+                t.rows_per_wave = R;
+                t.waves_per_group = w;
+                t.groups = 0;
+                t.schedule = BTE_BATCH_WIDE;
+                cand.push_back(t);
+            }
+    bte_batch_tuning best{};
+    double best_rate = -1.0;
+    const int ns = static_cast<int>(sample.size());
+    for (const bte_batch_tuning& t : cand) {
+        bte_batch* b = nullptr;
+        st = bte_batch_create(&c, ns, sample.data(), &t, nullptr, 0, hip_stream, &b);
+        if (st != BTE_OK) return st;
+        double secs = 1e300;
+        // the first run includes the graph capture; time the second
+        for (int rep = 0; rep < 2 && st == BTE_OK; ++rep) {
+            const auto t0 = std::chrono::steady_clock::now();
+            st = bte_batch_run(b);
+            const auto t1 = std::chrono::steady_clock::now();
+            secs = std::chrono::duration<double>(t1 - t0).count();
+        }
+        bte_batch_destroy(b);
+        if (st != BTE_OK) return st;
+        const double rate = work / secs;
+        if (rate > best_rate) {
+            best_rate = rate;
+            best = t;
+        }
+    }
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        g_tune_cache[key] = {best, best_rate};
+    }
+    *out = best;
+    if (cell_steps_per_s) *cell_steps_per_s = best_rate;
     return BTE_OK;
 }
 

@@ -49,11 +49,19 @@ def sweep_states(instances, nx, phiy, dt, precision=bte.BTE_FP32_BULK, tol=1e-6,
 
 
 def sweep(instances, nx, phiy, dt, warm=None, precision=bte.BTE_FP32_BULK, tol=1e-6,
-          max_periods=400, log=None, confirm=1, schedule=None):
-    """Run a batched sweep (cold, or warm from coefficients); (results, seconds)."""
+          max_periods=400, log=None, confirm=1, schedule=None, autotune=False,
+          tuning_cache=None, info=None):
+    """Run a batched sweep (cold, or warm from coefficients); (results, seconds).
+    With autotune the tile comes from the sweep autotuner (outside the timed
+    run); `info`, a dict, receives the tile and the tuner's sample rate."""
     cfg = bte.make_batch_config(nx, -phiy, phiy, dt, precision=precision, tol=tol,
                                 min_periods=2, max_periods=max_periods, confirm=confirm)
-    b = bte.Batch(cfg, instances, schedule=schedule)
+    b = bte.Batch(cfg, instances, schedule=schedule, autotune=autotune,
+                  tuning_cache=tuning_cache)
+    if info is not None:
+        t = b.get_tuning()
+        info.update(kernel=t.kernel, rows_per_wave=t.rows_per_wave,
+                    waves_per_group=t.waves_per_group, tuner_cell_steps_per_s=b.tune_rate)
     b.set_warm_start(warm)
     secs = b.run(log=log)
     res = b.results()

@@ -100,6 +100,10 @@ int main()
     CHECK(bte_batch_workspace_bytes(&c, 2, ib, &bt, &bytes) == BTE_EINVAL);
     bte_batch_tuning btb = bt; btb.waves_per_group = 3;
     CHECK(bte_batch_workspace_bytes(&c, 2, in, &btb, &bytes) == BTE_EINVAL);
+    bte_batch_tuning tuned{};
+    CHECK(bte_batch_tune(&cb, 2, in, nullptr, 1, &tuned, nullptr) == BTE_EINVAL);
+    CHECK(bte_batch_tune(&c, 2, ib, nullptr, 1, &tuned, nullptr) == BTE_EINVAL);
+    CHECK(bte_batch_tune(&c, 2, in, nullptr, 1, nullptr, nullptr) == BTE_EINVAL);
     CHECK(bte_batch_run(nullptr) == BTE_EINVAL);
     int32_t left = 0;
     CHECK(bte_batch_advance(nullptr, 1, &left) == BTE_EINVAL);

@@ -122,6 +122,19 @@ def test_batch_workspace_bytes_and_validation():
     assert bte.bte_batch_workspace_bytes(_cfg(), inst, w) < bte.bte_batch_workspace_bytes(_cfg(), inst, t)
 
 
+def test_batch_tune_host_validation():
+    """The sweep autotuner validates the batch before any device work."""
+    for cfg, inst in [(_cfg(min_periods=1), [_W()]), (_cfg(), [_W(omega=0.0)]),
+                      (_cfg(), [_W(B=1e4)])]:
+        with pytest.raises(bte.BteError) as ei:
+            bte.bte_batch_tune(cfg, inst)
+        assert ei.value.status == bte.BTE_EINVAL
+    with pytest.raises(bte.BteError) as ei:
+        bte.bte_batch_tune(_cfg(), [])
+    assert ei.value.status == bte.BTE_EINVAL
+    assert bte.tuning_cache_key(_cfg(), [_W(ny=41), _W(ny=11), _W(ny=41)]).endswith("ny11,41")
+
+
 def test_mlp_library_exports_and_host_validation():
     from paper_1401_6047_amd import mlp
     names = bte.header_functions(mlp.HEADER_PATH)

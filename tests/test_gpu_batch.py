@@ -263,3 +263,41 @@ def test_wide_schedule_period_cap_and_repeat_runs(bte, small):
     for w, r in zip(small, res[WIDE]):
         L = int(np.rint(2.0 * math.pi / (w.omega * w.dt)))
         assert r["converged"] == 0 and r["periods"] == 3 and r["steps"] == 3 * L
+
+
+def test_sweep_autotuner_picks_a_legal_shape_and_caches_it(bte, small, tmp_path):
+    """bte_batch_tune times a sample of the batch for each candidate tile and
+    returns one of them; the same (N_x, N_y set, precision) comes back from
+    the cache without measuring; a batch run with the tuned tile gives the
+    same FP64 results as with the default tile (every form and shape rounds
+    alike in FP64); the JSON cache of the binding round-trips."""
+    import time
+    w0 = small[0]
+    cfg = bte.make_batch_config(w0.nx, w0.phiy_min, w0.phiy_max, w0.dt, precision=0, tol=1e-6,
+                                min_periods=2, max_periods=60)
+    t, rate = bte.bte_batch_tune(cfg, small, use_cache=False)
+    print(f"tuned: kernel {t.kernel} R{t.rows_per_wave} W{t.waves_per_group}, "
+          f"{rate / 1e9:.1f} G cell-steps/s", flush=True)
+    assert t.kernel in (bte.BTE_KERNEL_FUSED, bte.BTE_KERNEL_FUSED2)
+    assert t.waves_per_group in (2, 4, 8) and t.schedule == bte.BTE_BATCH_WIDE
+    assert any(t.rows_per_wave == -(-w0.nx // c) for c in range(1, 9))
+    assert rate > 0
+    t0 = time.perf_counter()
+    t2, rate2 = bte.bte_batch_tune(cfg, list(reversed(small)))
+    assert time.perf_counter() - t0 < 0.5
+    assert (t2.kernel, t2.rows_per_wave, t2.waves_per_group) == \
+        (t.kernel, t.rows_per_wave, t.waves_per_group) and rate2 == rate
+    ref = run_batch(bte, small, precision=0)
+    path = str(tmp_path / "tune.json")
+    b = bte.Batch(cfg, small, autotune=True, tuning_cache=path)
+    got_t = b.get_tuning()
+    b.run(log=None)
+    got = b.results()
+    b.close()
+    assert (got_t.kernel, got_t.rows_per_wave, got_t.waves_per_group) == \
+        (t.kernel, t.rows_per_wave, t.waves_per_group)
+    for x, y in zip(got, ref):
+        assert x["absorption"] == y["absorption"] and x["periods"] == y["periods"]
+    b2 = bte.Batch(cfg, small, autotune=True, tuning_cache=path)
+    assert b2.tune_rate == pytest.approx(rate)
+    b2.close()
