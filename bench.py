@@ -21,6 +21,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -39,6 +40,8 @@ FP64_PEAK_TFLOPS = 78.6
 VALUES_PER_CELL = {0: 8, 1: 6, 2: 8, 3: 8}   # kernel form -> state values moved per launch
 KERNEL_NAMES = {0: "k_fused_step", 1: "k_half_step", 2: "k_fused_step2", 3: "k_fused_step3"}
 FORM_NAMES = {"fused": 0, "two_pass": 1, "fused2": 2, "fused3": 3, "auto": -1}
+# passes over the warm-start network's training states in the sweep leg
+WARM_EPOCHS = 60
 
 
 def launches_for(kernel, steps):
@@ -71,13 +74,106 @@ def parse():
                     help="instances of the batched-sweep measurement (0: skip)")
     ap.add_argument("--sweep-fp64", type=int, default=12,
                     help="draws the plain FP64 solver also runs (split evenly over the mu classes)")
-    ap.add_argument("--warm-train", type=int, default=2048,
+    ap.add_argument("--warm-train", type=int, default=16384,
                     help="coarse-grid training states for the warm-started sweep (0: no warm run)")
     ap.add_argument("--reconstruct", type=int, default=512,
                     help="phi_x samples of the timed f(phi_x, phi_y) reconstruction (0: skip)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
+    ap.add_argument("--full-run", choices=("fp64", "fp32"), default=None,
+                    help="instead of timing: integrate the workload from f0 over "
+                         "--full-periods ac periods in this precision and report the "
+                         "observables over the last --full-avg periods")
+    ap.add_argument("--full-periods", type=int, default=500)
+    ap.add_argument("--full-avg", type=int, default=10)
+    ap.add_argument("--full-until", type=int, default=0,
+                    help="stop after this many periods and write --full-ckpt (0: run to the end)")
+    ap.add_argument("--full-ckpt", default="", help="checkpoint (.npz) written when stopping early")
+    ap.add_argument("--full-resume", default="", help="checkpoint (.npz) to resume from")
     return ap.parse_args()
+
+
+def full_run(bte, torch, w, precision, args):
+    """One long trajectory of the workload (e.g. 500 ac periods of the large
+    instance), with the averaging window over its last periods (R14: n_end =
+    round(P T/dt), lo = n_end - round(K T/dt)).  It can stop at a period
+    boundary and write the whole state (both grids, exact in the solver's
+    storage precision) to a checkpoint, and resume from one, so that a run
+    longer than one job can be split; a resumed run is bitwise the
+    uninterrupted one.  Prints progress to stderr about once a minute."""
+    import numpy as np
+    L = 2.0 * math.pi / (w.omega * w.dt)
+    n_end = round(args.full_periods * L)
+    lo = n_end - round(args.full_avg * L)
+    target = round(args.full_until * L) if args.full_until else n_end
+    if target > lo and target != n_end:
+        raise SystemExit("--full-until must end before the averaging window starts")
+    s = bte.Solver.from_workload(w, precision=precision)
+    if args.full_resume:
+        ck = np.load(args.full_resume)
+        k0 = int(ck["step"])
+        norm0 = float(ck["norm0"])
+        assert int(ck["precision"]) == precision and str(ck["workload"]) == w.name
+        # the launch shape of the first segment (in FP32 bulk the rounding
+        # bits depend on how steps are grouped into launches)
+        kt, kr, kw, kg = (int(x) for x in ck["tuning"])
+        s.set_tuning(kernel=kt, rows_per_wave=kr, waves_per_block=kw, graph_steps=kg)
+        s.set_state(*(ck[x].astype(np.float64) for x in ("a_h", "b_h", "a_f", "b_f")), step=k0)
+    else:
+        s.autotune()
+        k0 = 0
+        norm0 = s.observables().norm
+    t = s.tuning()
+    s.set_window(lo, n_end)
+    log = lambda *a: print(*a, file=sys.stderr, flush=True)
+    log(f"full run {w.name} {args.full_run}: steps {k0} -> {target} of {n_end} "
+        f"(window {lo} < k <= {n_end}), kernel {t.kernel} R{t.rows_per_wave} W{t.waves_per_block}")
+    period = max(1, round(L))
+    t0 = time.perf_counter()
+    last = t0
+    k = k0
+    status = "ok"
+    try:
+        while k < target:
+            n = min(period, target - k)
+            s.step(n)
+            k += n
+            # one period in flight at a time (the step calls only queue work)
+            torch.cuda.synchronize()
+            now = time.perf_counter()
+            if now - last >= 45.0:
+                log(f"  step {k} of {target} ({k / L:.1f} periods), {now - t0:.0f} s, "
+                    f"{(now - t0) * 1e6 / (k - k0):.2f} us/step")
+                last = now
+        torch.cuda.synchronize()
+    except bte.BteError as e:
+        status = f"stopped: {e}"
+    wall = time.perf_counter() - t0
+    out = {"workload": w.name, "precision": args.full_run, "kernel": KERNEL_NAMES[t.kernel],
+           "tuning": {"kernel": t.kernel, "rows_per_wave": t.rows_per_wave,
+                      "waves_per_block": t.waves_per_block, "graph_steps": t.graph_steps},
+           "periods": args.full_periods, "avg_periods": args.full_avg, "n_end": n_end,
+           "window": [lo, n_end], "from_step": k0, "to_step": k, "wall_s": wall,
+           "us_per_step": wall * 1e6 / max(1, k - k0), "status": status}
+    o = s.observables()
+    out.update(norm=o.norm, norm0=norm0, norm_dev=abs(o.norm - norm0) / abs(norm0),
+               v_dr=o.v_dr, edge_mass=o.edge_mass, top_harm_mass=o.top_harm_mass,
+               obs_status=int(o.status))
+    if k < n_end and status == "ok" and args.full_ckpt:
+        st = s.state()
+        dt = np.float32 if precision == 1 else np.float64
+        np.savez_compressed(args.full_ckpt, step=k, norm0=norm0, precision=precision,
+                            workload=w.name,
+                            tuning=np.array([t.kernel, t.rows_per_wave, t.waves_per_block,
+                                             t.graph_steps]),
+                            **{x: a.astype(dt) for x, a in zip(("a_h", "b_h", "a_f", "b_f"), st)})
+        out["checkpoint"] = args.full_ckpt
+        out["checkpoint_bytes"] = os.path.getsize(args.full_ckpt)
+    elif k == n_end:
+        out.update(n_avg=int(o.n_avg), v_avg=o.v_avg, absorption=o.absorption,
+                   absorption_cov=o.absorption_cov)
+    s.close()
+    print(json.dumps({"full_run": out}), flush=True)
 
 
 def time_solver(bte, torch, w, precision, kernel, steps, warmup, autotune=True, shape=None):
@@ -203,6 +299,31 @@ def counter_traffic(kernel, precision, tuning):
     return None
 
 
+def counter_valu_busy(kernel, precision, tuning):
+    """VALU busy fraction of the step kernel from a committed SQ-counter
+    summary (profiles/*_sq_counters.txt: SQ_ACTIVE_INST_VALU over the CUs'
+    cycles), or None when none matches this kernel, precision, launch shape
+    and kernel sources."""
+    import glob
+    want = kernel_source_hash()
+    for path in sorted(glob.glob(os.path.join(HERE, "profiles", "*_sq_counters.txt"))):
+        kv = {}
+        with open(path) as f:
+            for line in f:
+                if ":" in line and not line.startswith("#"):
+                    k, v = line.split(":", 1)
+                    kv[k.strip()] = v.strip()
+        try:
+            if (kv.get("kernel") == kernel and kv.get("precision") == precision
+                    and int(kv.get("rows_per_wave", -1)) == tuning["rows_per_wave"]
+                    and int(kv.get("waves_per_block", -1)) == tuning["waves_per_block"]
+                    and kv.get("source_sha256") == want):
+                return float(kv["valu_busy"])
+        except (KeyError, ValueError):
+            continue
+    return None
+
+
 def cpu_model():
     """The host CPU's model name (first 'model name' line of /proc/cpuinfo)."""
     try:
@@ -281,18 +402,32 @@ def sweep_bench(bte, torch, n, n_fp64, n_train, log):
             s.close()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ref = []
+    ref, sub_times = [], []
     for w in sub:
+        t1 = time.perf_counter()
         s = bte.Solver.from_workload(w)
         bte.bte_set_tuning(s.handle, tunings[w.ny])
         ref.append(s.run_periods(tol=1e-6, max_periods=400, confirm=2))
         s.close()
+        sub_times.append(time.perf_counter() - t1)
     torch.cuda.synchronize()
     t_fp64 = time.perf_counter() - t0
     log(f"  fp64 solver: {len(sub)} instances in {t_fp64:.1f} s")
-    sub_res, t_sub = warmstart.sweep(sub, nx, phi, dt, log=log, confirm=2)
+    # the batch's tile from the sweep autotuner (a sample of these draws, timed
+    # per candidate shape before any sweep clock starts; cached per N_y set)
+    t0 = time.perf_counter()
+    tile = {}
+    cfg = bte.make_batch_config(nx, -phi, phi, dt, precision=bte.BTE_FP32_BULK, tol=1e-6,
+                                min_periods=2, max_periods=400, confirm=2)
+    bt, rate = bte.bte_batch_tune(cfg, draws)
+    t_tune = time.perf_counter() - t0
+    log(f"  sweep tuner: kernel {bt.kernel}, {bt.rows_per_wave} harmonics per wave, "
+        f"{bt.waves_per_group} waves per group ({rate / 1e9:.0f} G cell-steps/s on its sample, "
+        f"{t_tune:.1f} s)")
+    sub_res, t_sub = warmstart.sweep(sub, nx, phi, dt, log=log, confirm=2, autotune=True)
     log(f"  batched fp32 on the same {len(sub)} instances: {t_sub:.1f} s")
-    cold, t_cold = warmstart.sweep(draws, nx, phi, dt, log=log, confirm=2)
+    cold, t_cold = warmstart.sweep(draws, nx, phi, dt, log=log, confirm=2, autotune=True,
+                                   info=tile)
     log(f"  batched fp32 cold: {n} instances in {t_cold:.1f} s")
 
     def max_dA(res):
@@ -310,7 +445,25 @@ def sweep_bench(bte, torch, n, n_fp64, n_train, log):
     out["batched_fp32"] = {"instances": n, "wall_s": t_cold, "value": n / t_cold * 3600,
                            "periods_mean": sum(r["periods"] for r in cold) / n,
                            "converged": sum(r["converged"] for r in cold),
-                           "abs_dA_vs_fp64_max": max_dA([cold[i] for i in sub_idx])}
+                           "abs_dA_vs_fp64_max": max_dA([cold[i] for i in sub_idx]),
+                           "tile": tile, "tune_s": t_tune}
+    # The plain FP64 solver on all n draws, projected from its measured rate:
+    # per N_y class, the subset's wall time per cell-step, times the cell-steps
+    # each draw needs (the periods its batched run took, L = round(T/dt) steps
+    # each).  A projection from the measured subset, not a measurement.
+    def cell_steps(w, periods):
+        return w.nx * w.ny * periods * round(2 * math.pi / (w.omega * w.dt))
+    per_class = {}
+    for w, r, secs in zip(sub, ref, sub_times):
+        c = per_class.setdefault(w.ny, [0.0, 0.0])
+        c[0] += secs
+        c[1] += cell_steps(w, r["periods"])
+    proj = sum(cell_steps(w, r["periods"]) * per_class[w.ny][0] / per_class[w.ny][1]
+               for w, r in zip(draws, cold))
+    out["fp64_solver_projected_all_draws"] = {
+        "instances": n, "wall_s": proj, "value": n / proj * 3600,
+        "how": "per-N_y-class seconds per cell-step of the measured fp64 subset x the "
+               "cell-steps each draw's batched run took"}
     if n_train > 0:
         train = warmstart.coarse_draws(n_train, W.SWEEP_SEED + 101)
         t0 = time.perf_counter()
@@ -320,7 +473,7 @@ def sweep_bench(bte, torch, n, n_fp64, n_train, log):
         from paper_1401_6047_amd import mlp as M
         feats = M.features_of([train[i] for i in keep.tolist()])
         net, hist, _ = warmstart.train_network(feats, states.index_select(0, keep).contiguous(),
-                                               epochs=40, seed=W.SWEEP_SEED + 102)
+                                               epochs=WARM_EPOCHS, seed=W.SWEEP_SEED + 102)
         torch.cuda.synchronize()
         t_prep = time.perf_counter() - t0
         t0 = time.perf_counter()
@@ -328,7 +481,8 @@ def sweep_bench(bte, torch, n, n_fp64, n_train, log):
         torch.cuda.synchronize()
         t_inf = time.perf_counter() - t0
         net.close()
-        warm, t_warm = warmstart.sweep(draws, nx, phi, dt, warm=pred, log=log, confirm=2)
+        warm, t_warm = warmstart.sweep(draws, nx, phi, dt, warm=pred, log=log, confirm=2,
+                                       autotune=True)
         log(f"  batched fp32 warm: {n} instances in {t_warm:.1f} s "
             f"(+{t_inf * 1e3:.0f} ms inference; training data + training {t_prep:.1f} s)")
         pc = sum(r["periods"] for r in cold)
@@ -342,11 +496,12 @@ def sweep_bench(bte, torch, n, n_fp64, n_train, log):
             "abs_dA_vs_cold_max": max(abs(a["absorption"] - b["absorption"])
                                       for a, b in zip(cold, warm)),
             "network": {"train_states": len(keep), "train_grid": "N_x 48, N_y 101/201/401, dt 1e-3",
-                        "epochs": 40, "final_loss": hist[-1], "prep_s": t_prep}}
+                        "epochs": WARM_EPOCHS, "final_loss": hist[-1], "prep_s": t_prep}}
     best = out.get("batched_fp32_warm", out["batched_fp32"])
     out["value"] = best["value"]
     out["vs_fp64_solver_same_draws"] = (out["batched_fp32_same_draws"]["value"]
                                         / out["fp64_solver"]["value"])
+    out["vs_fp64_solver_projected"] = best["value"] / out["fp64_solver_projected_all_draws"]["value"]
     return out
 
 
@@ -365,6 +520,9 @@ def main():
     from paper_1401_6047_amd import workloads as W
 
     w = W.WORKLOADS[args.workload]
+    if args.full_run:
+        full_run(bte, torch, w, 1 if args.full_run == "fp32" else 0, args)
+        return
     precision = 1 if args.precision == "fp32" else 0
     kernel = FORM_NAMES[args.kernel]
     at = not args.no_autotune
@@ -408,6 +566,10 @@ def main():
                      "traffic": counter_traffic(main_run["kernel"], args.precision,
                                                 main_run["tuning"]),
                      "kernel": main_run["kernel"],
+                     "valu_busy": counter_valu_busy(main_run["kernel"], args.precision,
+                                                    main_run["tuning"]),
+                     "limiter": "VALU instruction issue (SQ counters); the HBM traffic "
+                                "is hidden under it",
                      "steps_per_launch": main_run["steps_per_launch"],
                      "bytes_per_launch": main_run["bytes_per_launch"],
                      "avg_launch_us": main_run["avg_launch_us"]},
