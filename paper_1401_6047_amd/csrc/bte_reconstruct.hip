@@ -210,10 +210,130 @@ hipError_t launch_shape(hipStream_t stream, const T* a, const T* b, int64_t ld, 
 // row of instructions per wavefront (more rows cost occupancy); 32 points
 // with loads 8 steps ahead up to ~768 samples (43.6 TFLOP/s at 512), 64
 // points 4 steps ahead beyond (50.1 TFLOP/s at 1024).
+// ---- power-of-two sample counts: one FFT per phi_y column ------------------------
+// With x_j = -pi + 2 pi j / M, e^{i n x_j} = (-1)^n w^{n j}, w = e^{2 pi i / M},
+// so f[j][m] = Re sum_k C_k(m) w^{j k} with the folded coefficients
+//     C_k(m) = sum_{n < N_x, n = k mod M} (-1)^n (a_n(m) - i b_n(m)),
+// an inverse DFT of length M per column.  f is real, so two columns share one
+// complex transform: with H_k = (C_k + conj(C_{-k})) / 2 (the Hermitian part,
+// whose transform is Re of C's), the transform of H(m) + i H(m') is
+// f(m) + i f(m').  A workgroup owns 2P consecutive columns (P pairs; P = 8
+// up to M = 256, then 4 and 2, so that the sequences and the twiddles stay
+// within 64 KiB of LDS): it builds the P sequences in LDS in bit-reversed
+// order, runs log2 M radix-2 decimation-in-time stages over them with a
+// shared twiddle table w^t = e^{2 pi i t / M} (sincospi of an exact
+// fraction), and writes each sample row as 2P consecutive doubles.  O(M log M) work per column instead
+// of O(M N_x); the coefficients are read once from memory (the reads for
+// k and -k of the same row hit the cache), and the output is written once.
+constexpr int kFftThreads = 256;
+constexpr int kFftMaxM = 1024;
+
+__device__ __forceinline__ int bit_reverse(int k, int bits)
+{
+    return static_cast<int>(__builtin_bitreverse32(static_cast<uint32_t>(k)) >> (32 - bits));
+}
+
+template <typename T, int kFftPairs>
+__global__ __launch_bounds__(kFftThreads) void k_reconstruct_fft(const T* __restrict__ a,
+                                                                 const T* __restrict__ b,
+                                                                 int64_t ld, int nx, int ny,
+                                                                 int M, int logM,
+                                                                 double* __restrict__ out)
+{
+    constexpr int kFftCols = 2 * kFftPairs;
+    extern __shared__ double lds[];
+    double2* z = reinterpret_cast<double2*>(lds);              // [kFftPairs][M]
+    double2* tw = z + static_cast<size_t>(kFftPairs) * M;      // [M / 2]
+    const int m0 = blockIdx.x * kFftCols;
+    const int tid = threadIdx.x;
+
+    for (int t = tid; t < M / 2; t += kFftThreads) {
+        double sn, cs;
+        sincospi(2.0 * t / M, &sn, &cs);
+        tw[t] = make_double2(cs, sn);
+    }
+    // Hermitian parts of both columns of a pair, bit-reversed into place.
+    // Thread (k, p): pair p of the 8 (columns m0 + 2p, m0 + 2p + 1).
+    for (int idx = tid; idx < M * kFftPairs; idx += kFftThreads) {
+        const int p = idx % kFftPairs;
+        const int k = idx / kFftPairs;
+        const int km = (M - k) & (M - 1);
+        const int c0 = m0 + 2 * p, c1 = c0 + 1;
+        double2 h[2] = {make_double2(0.0, 0.0), make_double2(0.0, 0.0)};
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int c = q ? c1 : c0;
+            if (c >= ny) continue;
+            // (C_k + conj(C_{-k})) / 2: rows n = k mod M enter as
+            // s_n (a_n - i b_n), rows n = -k mod M as s_n (a_n + i b_n)
+            double re = 0.0, im = 0.0;
+            for (int n = k; n < nx; n += M) {
+                const double s = (n & 1) ? -1.0 : 1.0;
+                re += s * static_cast<double>(a[n * ld + c]);
+                if (n > 0) im -= s * static_cast<double>(b[n * ld + c]);
+            }
+            for (int n = km; n < nx; n += M) {
+                const double s = (n & 1) ? -1.0 : 1.0;
+                re += s * static_cast<double>(a[n * ld + c]);
+                if (n > 0) im += s * static_cast<double>(b[n * ld + c]);
+            }
+            h[q] = make_double2(0.5 * re, 0.5 * im);
+        }
+        // H(m) + i H(m')
+        z[p * M + bit_reverse(k, logM)] = make_double2(h[0].x - h[1].y, h[0].y + h[1].x);
+    }
+    __syncthreads();
+    // radix-2 decimation in time, in place
+    for (int s = 1; s <= logM; ++s) {
+        const int half = 1 << (s - 1);
+        const int tstride = M >> s;                          // twiddle index step
+        for (int idx = tid; idx < kFftPairs * (M / 2); idx += kFftThreads) {
+            const int p = idx / (M / 2);
+            const int r = idx % (M / 2);
+            const int g = (r / half) * (2 * half);
+            const int t = r % half;
+            double2* zp = z + p * M;
+            const double2 u = zp[g + t];
+            const double2 v0 = zp[g + t + half];
+            const double2 w = tw[t * tstride];
+            const double2 v = make_double2(v0.x * w.x - v0.y * w.y, v0.x * w.y + v0.y * w.x);
+            zp[g + t] = make_double2(u.x + v.x, u.y + v.y);
+            zp[g + t + half] = make_double2(u.x - v.x, u.y - v.y);
+        }
+        __syncthreads();
+    }
+    // row j of the output: 16 consecutive columns (real and imaginary parts
+    // of the 8 transforms)
+    for (int idx = tid; idx < M * kFftCols; idx += kFftThreads) {
+        const int c = idx % kFftCols;
+        const int j = idx / kFftCols;
+        const int m = m0 + c;
+        if (m >= ny) continue;
+        const double2 v = z[(c >> 1) * M + j];
+        out[static_cast<int64_t>(j) * ny + m] = (c & 1) ? v.y : v.x;
+    }
+}
+
 template <typename T>
 hipError_t launch_reconstruct(hipStream_t stream, const T* a, const T* b, int64_t ld, int nx,
                               int ny, int M, double* out)
 {
+    if (M >= 8 && M <= kFftMaxM && (M & (M - 1)) == 0) {
+        const int logM = __builtin_ctz(static_cast<unsigned>(M));
+        const int pairs = M <= 256 ? 8 : (M == 512 ? 4 : 2);
+        const size_t lds = (static_cast<size_t>(pairs) * M + M / 2) * sizeof(double2);
+        const int blocks = (ny + 2 * pairs - 1) / (2 * pairs);
+        if (pairs == 8)
+            hipLaunchKernelGGL((k_reconstruct_fft<T, 8>), dim3(blocks), dim3(kFftThreads), lds,
+                               stream, a, b, ld, nx, ny, M, logM, out);
+        else if (pairs == 4)
+            hipLaunchKernelGGL((k_reconstruct_fft<T, 4>), dim3(blocks), dim3(kFftThreads), lds,
+                               stream, a, b, ld, nx, ny, M, logM, out);
+        else
+            hipLaunchKernelGGL((k_reconstruct_fft<T, 2>), dim3(blocks), dim3(kFftThreads), lds,
+                               stream, a, b, ld, nx, ny, M, logM, out);
+        return hipGetLastError();
+    }
     if (M >= 768) return launch_shape<T, 1, 4, 4>(stream, a, b, ld, nx, ny, M, out);
     return launch_shape<T, 1, 2, 8>(stream, a, b, ld, nx, ny, M, out);
 }
