@@ -77,7 +77,10 @@ def parse():
     ap.add_argument("--warm-train", type=int, default=16384,
                     help="coarse-grid training states for the warm-started sweep (0: no warm run)")
     ap.add_argument("--reconstruct", type=int, default=512,
-                    help="phi_x samples of the timed f(phi_x, phi_y) reconstruction (0: skip)")
+                    help="phi_x samples of the timed f(phi_x, phi_y) reconstruction (0: skip; "
+                         "powers of two from 8 to 1024 run the FFT kernel)")
+    ap.add_argument("--reconstruct-direct", type=int, default=500,
+                    help="also time the direct-sum kernel at this many samples (0: skip)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     ap.add_argument("--full-run", choices=("fp64", "fp32"), default=None,
@@ -229,6 +232,30 @@ def time_solver(bte, torch, w, precision, kernel, steps, warmup, autotune=True, 
     return out
 
 
+def stream_copy_rate(bte, torch, mib=2048, reps=10):
+    """Read+write streaming rate of the library's plain copy kernel over two
+    buffers of `mib` MiB (HIP events on the current stream): the practical
+    HBM ceiling for a kernel that reads and writes its data once."""
+    n = mib << 20
+    src = torch.ones(n // 8, dtype=torch.float64, device="cuda")
+    dst = torch.zeros_like(src)
+    st = torch.cuda.current_stream()
+    for _ in range(2):
+        bte.bte_stream_copy(src.data_ptr(), dst.data_ptr(), n, st.cuda_stream)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(reps):
+        bte.bte_stream_copy(src.data_ptr(), dst.data_ptr(), n, st.cuda_stream)
+    e1.record(st)
+    torch.cuda.synchronize()
+    if not torch.equal(src[-1024:], dst[-1024:]):
+        raise RuntimeError("stream copy produced wrong data")
+    rate = 2.0 * n * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    return rate
+
+
 def reconstruct_bench(bte, torch, w, n_phix=512, launches=20):
     """f(phi_x, phi_y) reconstruction (Eq. f_fourier) of the workload's state
     on n_phix phi_x samples: average launch time by HIP events on the
@@ -248,6 +275,15 @@ def reconstruct_bench(bte, torch, w, n_phix=512, launches=20):
     torch.cuda.synchronize()
     s.close()
     us = start.elapsed_time(stop) * 1e3 / launches
+    if 8 <= n_phix <= 1024 and n_phix & (n_phix - 1) == 0:
+        # one FFT per phi_y column: bound by reading the coefficients once
+        # (a_n for n < N_x, b_n for 1 <= n < N_x) and writing the samples
+        nbytes = (2 * w.nx - 1) * w.ny * 8 + n_phix * w.ny * 8
+        gbs = nbytes / (us * 1e-6) / 1e9
+        return {"workload": f"{w.name} state, {n_phix} phi_x samples",
+                "kernel": "k_reconstruct_fft", "avg_launch_us": us, "bytes_per_launch": nbytes,
+                "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS,
+                             "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS}}
     flops = 4.0 * (w.nx - 1) * n_phix * w.ny
     tf = flops / (us * 1e-6) / 1e12
     return {"workload": f"{w.name} state, {n_phix} phi_x samples", "kernel": "k_reconstruct",
@@ -582,15 +618,18 @@ def main():
                             for k, v in variants.items()}
     if args.reconstruct > 0:
         line["reconstruct"] = reconstruct_bench(bte, torch, w, n_phix=args.reconstruct)
+    if args.reconstruct_direct > 0:
+        line["reconstruct_direct"] = reconstruct_bench(bte, torch, w,
+                                                       n_phix=args.reconstruct_direct)
+    # the practical ceiling: the library's own streaming copy (reads and
+    # writes every byte once, as the step kernels do)
+    practical = stream_copy_rate(bte, torch)
+    line["roofline"]["practical_peak_GBs"] = practical
+    line["roofline"]["frac_of_practical"] = main_run["achieved_GBs"] / practical
     if args.copy_mib > 0:
-        # a plain device-to-device copy of known size, for scaling the HBM
-        # traffic counters of the step kernel
-        n = args.copy_mib * (1 << 20) // 8
-        src = torch.ones(n, dtype=torch.float64, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(5):
-            dst.copy_(src)
-        torch.cuda.synchronize()
+        # a plain copy of known size for scaling the HBM traffic counters of
+        # the step kernel (k_stream_copy, 5 runs)
+        stream_copy_rate(bte, torch, mib=args.copy_mib, reps=5)
         line["copy_probe_mib"] = args.copy_mib
     if args.sweep > 0:
         line["sweep"] = sweep_bench(bte, torch, args.sweep, min(args.sweep_fp64, args.sweep),

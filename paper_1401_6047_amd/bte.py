@@ -138,6 +138,7 @@ def _load():
                                            vp], ctypes.c_int),
         "bte_run_periods": ([vp, ctypes.c_double, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                              P(bte_result)], ctypes.c_int),
+        "bte_stream_copy": ([vp, vp, ctypes.c_size_t, vp], ctypes.c_int),
         "bte_destroy": ([vp], None),
         "bte_last_error": ([], ctypes.c_char_p),
         "bte_version": ([], ctypes.c_char_p),
@@ -356,6 +357,12 @@ def bte_state_observables(a_ptr, b_ptr, n_x, n_y, ld, phiy_min, phiy_max, alpha,
                                       float(phiy_max), float(alpha), ctypes.c_void_p(ws_ptr or None),
                                       int(ws_bytes), ctypes.c_void_p(stream_ptr or None),
                                       ctypes.c_void_p(out_ptr or None)), "bte_state_observables")
+
+
+def bte_stream_copy(src_ptr, dst_ptr, nbytes, stream_ptr=0):
+    _check(_lib.bte_stream_copy(ctypes.c_void_p(src_ptr or None), ctypes.c_void_p(dst_ptr or None),
+                                int(nbytes), ctypes.c_void_p(stream_ptr or None)),
+           "bte_stream_copy")
 
 
 STATE_OBS_NOALLOC_MAX_NX = 16384   # BTE_STATE_OBS_NOALLOC_MAX_NX of include/bte.h

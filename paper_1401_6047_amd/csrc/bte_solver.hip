@@ -960,6 +960,23 @@ bte_status bte_state_observables_noalloc(const double* a, const double* b, int32
     return BTE_OK;
 }
 
+bte_status bte_stream_copy(const void* src, void* dst, size_t bytes, void* hip_stream)
+{
+    if (!src || !dst) return fail(BTE_EINVAL, "src and dst must not be NULL");
+    if (bytes % 16 || reinterpret_cast<uintptr_t>(src) % 16 || reinterpret_cast<uintptr_t>(dst) % 16)
+        return fail(BTE_EINVAL, "bytes and both buffers must be multiples of 16");
+    const char* a = static_cast<const char*>(src);
+    const char* b = static_cast<const char*>(dst);
+    if (a < b + bytes && b < a + bytes) return fail(BTE_EINVAL, "src and dst overlap");
+    if (bytes == 0) return BTE_OK;
+    int dev = 0, cus = 256;
+    HIP_TRY(hipGetDevice(&dev));
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    HIP_TRY(bte::launch_stream_copy(src, dst, bytes, 8 * std::max(cus, 1),
+                                    static_cast<hipStream_t>(hip_stream)));
+    return BTE_OK;
+}
+
 void bte_destroy(bte_solver* s)
 {
     if (!s) return;

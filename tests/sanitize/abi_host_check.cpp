@@ -114,6 +114,8 @@ int main()
     CHECK(bte_mlp_workspace_bytes(0, 0) == 0);
     bte_mlp* m = nullptr;
     CHECK(bte_mlp_create(0, 0, nullptr, 0, nullptr, &m) != BTE_OK);
+    CHECK(bte_stream_copy(nullptr, fake, 16, nullptr) == BTE_EINVAL);
+    CHECK(bte_stream_copy(fake, fake + 1, 16, nullptr) == BTE_EINVAL);
     CHECK(std::strlen(bte_version()) > 0);
     CHECK(bte_last_error() != nullptr);
     std::printf("abi host sanitizer run ok\n");

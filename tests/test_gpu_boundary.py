@@ -216,3 +216,22 @@ def test_state_observables_rejects_bad_arguments(bte):
     with pytest.raises(bte.BteError) as ei:
         bte.bte_state_observables(p, p, 4, 10, 10, -1, 1, 1, wp, need - 8, 0, out.data_ptr())
     assert ei.value.status == bte.BTE_ENOMEM
+
+
+def test_stream_copy_copies_and_validates(bte):
+    """bte_stream_copy (the measurement copy): exact bytes for sizes with and
+    without a remainder of its four-way unrolled loop; rejects overlap and
+    misalignment."""
+    import torch
+    for n in (16, 4096 * 16 + 48, 3 << 20):
+        src = torch.randint(0, 255, (n,), dtype=torch.uint8, device="cuda")
+        dst = torch.zeros_like(src)
+        bte.bte_stream_copy(src.data_ptr(), dst.data_ptr(), n, torch.cuda.current_stream().cuda_stream)
+        torch.cuda.synchronize()
+        assert torch.equal(src, dst)
+    buf = torch.zeros(1024, dtype=torch.uint8, device="cuda")
+    for args in [(buf.data_ptr(), buf.data_ptr() + 256, 512), (buf.data_ptr() + 8, buf.data_ptr() + 512, 256),
+                 (buf.data_ptr(), buf.data_ptr() + 512, 100)]:
+        with pytest.raises(bte.BteError) as ei:
+            bte.bte_stream_copy(*args)
+        assert ei.value.status == bte.BTE_EINVAL
