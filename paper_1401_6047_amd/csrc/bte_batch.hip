@@ -488,40 +488,51 @@ __global__ __launch_bounds__(kMaxWavesPerGroup * kWave) void k_wide_setup(BatchA
 }
 
 // Block -> instance table of the next pass, and the count still running.
-__global__ __launch_bounds__(1024) void k_wide_scan(WideArgs W, int n)
+// One block of kScanThreads: each thread sums a contiguous run of instances,
+// the runs are scanned with wavefront shuffles and the wavefront totals
+// through LDS (integer sums, so the order does not matter).
+constexpr int kScanThreads = 1024;
+__global__ __launch_bounds__(kScanThreads) void k_wide_scan(WideArgs W, int n)
 {
-    __shared__ int s_part[1024];
-    __shared__ int s_left;
-    const int t = threadIdx.x, nt = blockDim.x;
-    const int per = (n + nt - 1) / nt;
+    constexpr int kWaves = kScanThreads / kWave;
+    __shared__ int s_wsum[kWaves];
+    __shared__ int s_wleft[kWaves];
+    const int t = threadIdx.x;
+    const int per = (n + kScanThreads - 1) / kScanThreads;
     const int lo = min(t * per, n), hi = min(lo + per, n);
     int sum = 0, left = 0;
     for (int i = lo; i < hi; ++i) {
         sum += W.st[i].nblocks;
         left += W.st[i].done ? 0 : 1;
     }
-    s_part[t] = sum;
-    if (t == 0) s_left = 0;
-    __syncthreads();
-    atomicAdd(&s_left, left);
-    if (t == 0) {
-        int acc = 0;
-        for (int j = 0; j < nt; ++j) {
-            const int v = s_part[j];
-            s_part[j] = acc;
-            acc += v;
-        }
-        W.first[n] = acc;
+    const int lane = t & (kWave - 1), w = t / kWave;
+    int x = sum;                                  // inclusive scan within the wavefront
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        const int y = __shfl_up(x, off);
+        if (lane >= off) x += y;
     }
+    int l = left;
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) l += __shfl_xor(l, off);
+    if (lane == kWave - 1) s_wsum[w] = x;
+    if (lane == 0) s_wleft[w] = l;
     __syncthreads();
-    int acc = s_part[t];
+    int base = 0;
+    for (int j = 0; j < w; ++j) base += s_wsum[j];
+    if (t == kScanThreads - 1) W.first[n] = base + x;
+    int acc = base + x - sum;                     // exclusive prefix of this thread's run
     for (int i = lo; i < hi; ++i) {
         W.first[i] = acc;
         const int nb = W.st[i].nblocks;
         for (int j = 0; j < nb; ++j) W.owner[acc + j] = i;
         acc += nb;
     }
-    if (t == 0) W.remaining[0] = s_left;
+    if (t == 0) {
+        int L = 0;
+        for (int j = 0; j < kWaves; ++j) L += s_wleft[j];
+        W.remaining[0] = L;
+    }
 }
 
 // One pass: workgroup b runs tiles of the instance whose block range holds b.
@@ -870,7 +881,7 @@ hipError_t capture_wide_setup(bte_batch* b)
     const bte::WideArgs W = wide_args(b);
     hipLaunchKernelGGL(bte::k_wide_setup<T>, dim3(b->n), dim3(b->tune.waves_per_group * bte::kWave),
                        0, b->capture_stream, A, W);
-    hipLaunchKernelGGL(bte::k_wide_scan, dim3(1), dim3(1024), 0, b->capture_stream, W, b->n);
+    hipLaunchKernelGGL(bte::k_wide_scan, dim3(1), dim3(bte::kScanThreads), 0, b->capture_stream, W, b->n);
     return hipGetLastError();
 }
 
@@ -884,7 +895,7 @@ hipError_t capture_wide_passes(bte_batch* b)
                            dim3(b->tune.waves_per_group * bte::kWave), 0, b->capture_stream, A, W);
         hipLaunchKernelGGL(bte::k_wide_book<T>, dim3(b->n), dim3(bte::kWave), 0, b->capture_stream,
                            A, W);
-        hipLaunchKernelGGL(bte::k_wide_scan, dim3(1), dim3(1024), 0, b->capture_stream, W, b->n);
+        hipLaunchKernelGGL(bte::k_wide_scan, dim3(1), dim3(bte::kScanThreads), 0, b->capture_stream, W, b->n);
     }
     return hipGetLastError();
 }

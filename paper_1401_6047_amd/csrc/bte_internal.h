@@ -156,10 +156,6 @@ hipError_t launch_state_observables(const Consts& cs, const double* a, const dou
                                    int edge_w, int top_from, double f, double* part,
                                    double* red, double* out, hipStream_t st);
 
-// Streaming copy of `bytes` (a multiple of 16) on `blocks` workgroups of 256.
-hipError_t launch_stream_copy(const void* src, void* dst, size_t bytes, int blocks,
-                              hipStream_t st);
-
 // Stability check of the state after a run of steps: if sum_m a_0(m) or
 // sum_m b_1(m) is not finite, or sum_m a_0 lies further from its equilibrium
 // value ctl->norm_eq than the initial state did (ctl->norm_ref) by more than

@@ -370,32 +370,6 @@ hipError_t launch_init_equilibrium(const Consts& cs, T* a, T* b, const double* s
     return hipGetLastError();
 }
 
-// Plain streaming copy, 16 bytes per access, four independent accesses in
-// flight per thread and turn of the grid-stride loop.
-__global__ __launch_bounds__(256) void k_stream_copy(const uint4* __restrict__ src,
-                                                     uint4* __restrict__ dst, size_t n16)
-{
-    const size_t stride = static_cast<size_t>(gridDim.x) * blockDim.x;
-    size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    for (; i + 3 * stride < n16; i += 4 * stride) {
-        const uint4 a = src[i], b = src[i + stride], c = src[i + 2 * stride],
-                    d = src[i + 3 * stride];
-        dst[i] = a;
-        dst[i + stride] = b;
-        dst[i + 2 * stride] = c;
-        dst[i + 3 * stride] = d;
-    }
-    for (; i < n16; i += stride) dst[i] = src[i];
-}
-
-hipError_t launch_stream_copy(const void* src, void* dst, size_t bytes, int blocks,
-                              hipStream_t st)
-{
-    hipLaunchKernelGGL(k_stream_copy, dim3(blocks), dim3(256), 0, st,
-                       static_cast<const uint4*>(src), static_cast<uint4*>(dst), bytes / 16);
-    return hipGetLastError();
-}
-
 hipError_t launch_advance_counter(Ctl* ctl, int64_t n, hipStream_t st)
 {
     hipLaunchKernelGGL(k_advance_counter, dim3(1), dim3(64), 0, st, ctl, n);

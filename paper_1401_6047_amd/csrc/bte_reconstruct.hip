@@ -221,10 +221,11 @@ hipError_t launch_shape(hipStream_t stream, const T* a, const T* b, int64_t ld, 
 // up to M = 256, then 4 and 2, so that the sequences and the twiddles stay
 // within 64 KiB of LDS): it builds the P sequences in LDS in bit-reversed
 // order, runs log2 M radix-2 decimation-in-time stages over them with a
-// shared twiddle table w^t = e^{2 pi i t / M} (sincospi of an exact
-// fraction), and writes each sample row as 2P consecutive doubles.  O(M log M) work per column instead
-// of O(M N_x); the coefficients are read once from memory (the reads for
-// k and -k of the same row hit the cache), and the output is written once.
+// shared twiddle table (each stage's e^{2 pi i t / 2^s} contiguous, sincospi
+// of an exact fraction), and writes each sample row as 2P consecutive
+// doubles.  O(M log M) work per column instead of O(M N_x); each coefficient
+// row is read once per column group, the groups sharing cache lines run on
+// one XCD, and the output is written once.
 constexpr int kFftThreads = 256;
 constexpr int kFftMaxM = 1024;
 
@@ -232,6 +233,11 @@ __device__ __forceinline__ int bit_reverse(int k, int bits)
 {
     return static_cast<int>(__builtin_bitreverse32(static_cast<uint32_t>(k)) >> (32 - bits));
 }
+
+// LDS position of entry i of a sequence: one 16-byte gap after every 8
+// entries, so that entries a multiple of 8 apart (the bit-reversed stores, the
+// early butterfly stages) fall in different banks.
+__device__ __forceinline__ int fft_pad(int i) { return i + (i >> 3); }
 
 template <typename T, int kFftPairs>
 __global__ __launch_bounds__(kFftThreads) void k_reconstruct_fft(const T* __restrict__ a,
@@ -242,63 +248,84 @@ __global__ __launch_bounds__(kFftThreads) void k_reconstruct_fft(const T* __rest
 {
     constexpr int kFftCols = 2 * kFftPairs;
     extern __shared__ double lds[];
-    double2* z = reinterpret_cast<double2*>(lds);              // [kFftPairs][M]
-    double2* tw = z + static_cast<size_t>(kFftPairs) * M;      // [M / 2]
-    const int m0 = blockIdx.x * kFftCols;
+    const int Mp = M + M / 8;                                  // padded sequence length
+    double2* z = reinterpret_cast<double2*>(lds);              // [kFftPairs][Mp]
+    double2* tw = z + static_cast<size_t>(kFftPairs) * Mp;     // [M - 1]
+    // blocks are dispatched round-robin over the 8 XCDs: give each XCD a
+    // contiguous run of column groups, so that the halves of a cache line two
+    // neighbouring groups read meet in one L2
+    const int nb = gridDim.x, per = (nb + kXcds - 1) / kXcds;
+    const int grp = (blockIdx.x % kXcds) * per + blockIdx.x / kXcds;
+    if (grp * kFftCols >= ny) return;
+    const int m0 = grp * kFftCols;
     const int tid = threadIdx.x;
 
-    for (int t = tid; t < M / 2; t += kFftThreads) {
+    // twiddles of stage s (butterfly span 2^s) stored contiguously from
+    // 2^{s-1} - 1: e^{2 pi i t / 2^s} for t < 2^{s-1}, so that the lanes of a
+    // stage read consecutive entries
+    for (int e = tid; e < M - 1; e += kFftThreads) {
+        const int sm1 = 31 - __builtin_clz(static_cast<unsigned>(e + 1));   // s - 1
+        const int t = e + 1 - (1 << sm1);
         double sn, cs;
-        sincospi(2.0 * t / M, &sn, &cs);
-        tw[t] = make_double2(cs, sn);
+        sincospi(static_cast<double>(t) / static_cast<double>(1 << sm1), &sn, &cs);
+        tw[e] = make_double2(cs, sn);
     }
     // Hermitian parts of both columns of a pair, bit-reversed into place.
-    // Thread (k, p): pair p of the 8 (columns m0 + 2p, m0 + 2p + 1).
-    for (int idx = tid; idx < M * kFftPairs; idx += kFftThreads) {
+    // H is Hermitian (H_{-k} = conj(H_k)), so thread (k, p) for k = 0 .. M/2
+    // reads the rows n = k and n = -k (mod M) once and writes both Z_k and
+    // Z_{-k}; all of its loads are independent of each other.
+    for (int idx = tid; idx < (M / 2 + 1) * kFftPairs; idx += kFftThreads) {
         const int p = idx % kFftPairs;
         const int k = idx / kFftPairs;
         const int km = (M - k) & (M - 1);
-        const int c0 = m0 + 2 * p, c1 = c0 + 1;
-        double2 h[2] = {make_double2(0.0, 0.0), make_double2(0.0, 0.0)};
+        const int c0 = m0 + 2 * p;
+        // C_k = sum_{n = k mod M} (-1)^n (a_n - i b_n), for both columns
+        double ck[2][2] = {{0.0, 0.0}, {0.0, 0.0}}, cm[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
-            const int c = q ? c1 : c0;
+            const int c = c0 + q;
             if (c >= ny) continue;
-            // (C_k + conj(C_{-k})) / 2: rows n = k mod M enter as
-            // s_n (a_n - i b_n), rows n = -k mod M as s_n (a_n + i b_n)
-            double re = 0.0, im = 0.0;
             for (int n = k; n < nx; n += M) {
                 const double s = (n & 1) ? -1.0 : 1.0;
-                re += s * static_cast<double>(a[n * ld + c]);
-                if (n > 0) im -= s * static_cast<double>(b[n * ld + c]);
+                ck[q][0] += s * static_cast<double>(a[n * ld + c]);
+                if (n > 0) ck[q][1] -= s * static_cast<double>(b[n * ld + c]);
             }
-            for (int n = km; n < nx; n += M) {
-                const double s = (n & 1) ? -1.0 : 1.0;
-                re += s * static_cast<double>(a[n * ld + c]);
-                if (n > 0) im += s * static_cast<double>(b[n * ld + c]);
+            if (km != k) {
+                for (int n = km; n < nx; n += M) {
+                    const double s = (n & 1) ? -1.0 : 1.0;
+                    cm[q][0] += s * static_cast<double>(a[n * ld + c]);
+                    if (n > 0) cm[q][1] -= s * static_cast<double>(b[n * ld + c]);
+                }
+            } else {
+                cm[q][0] = ck[q][0];
+                cm[q][1] = ck[q][1];
             }
-            h[q] = make_double2(0.5 * re, 0.5 * im);
         }
-        // H(m) + i H(m')
-        z[p * M + bit_reverse(k, logM)] = make_double2(h[0].x - h[1].y, h[0].y + h[1].x);
+        // H_k = (C_k + conj(C_{-k})) / 2 for both columns; Z = H(m) + i H(m')
+        const double h0r = 0.5 * (ck[0][0] + cm[0][0]), h0i = 0.5 * (ck[0][1] - cm[0][1]);
+        const double h1r = 0.5 * (ck[1][0] + cm[1][0]), h1i = 0.5 * (ck[1][1] - cm[1][1]);
+        z[p * Mp + fft_pad(bit_reverse(k, logM))] = make_double2(h0r - h1i, h0i + h1r);
+        if (km != k)   // Z_{-k} = conj(H_k(m)) + i conj(H_k(m'))
+            z[p * Mp + fft_pad(bit_reverse(km, logM))] = make_double2(h0r + h1i, h1r - h0i);
     }
     __syncthreads();
     // radix-2 decimation in time, in place
+    // (all sizes are powers of two: index arithmetic by shifts and masks)
     for (int s = 1; s <= logM; ++s) {
         const int half = 1 << (s - 1);
-        const int tstride = M >> s;                          // twiddle index step
+        const double2* tws = tw + (half - 1);                // this stage's twiddles
         for (int idx = tid; idx < kFftPairs * (M / 2); idx += kFftThreads) {
-            const int p = idx / (M / 2);
-            const int r = idx % (M / 2);
-            const int g = (r / half) * (2 * half);
-            const int t = r % half;
-            double2* zp = z + p * M;
-            const double2 u = zp[g + t];
-            const double2 v0 = zp[g + t + half];
-            const double2 w = tw[t * tstride];
+            const int p = idx >> (logM - 1);
+            const int r = idx & (M / 2 - 1);
+            const int g = (r >> (s - 1)) << s;
+            const int t = r & (half - 1);
+            double2* zp = z + p * Mp;
+            const double2 u = zp[fft_pad(g + t)];
+            const double2 v0 = zp[fft_pad(g + t + half)];
+            const double2 w = tws[t];
             const double2 v = make_double2(v0.x * w.x - v0.y * w.y, v0.x * w.y + v0.y * w.x);
-            zp[g + t] = make_double2(u.x + v.x, u.y + v.y);
-            zp[g + t + half] = make_double2(u.x - v.x, u.y - v.y);
+            zp[fft_pad(g + t)] = make_double2(u.x + v.x, u.y + v.y);
+            zp[fft_pad(g + t + half)] = make_double2(u.x - v.x, u.y - v.y);
         }
         __syncthreads();
     }
@@ -309,7 +336,7 @@ __global__ __launch_bounds__(kFftThreads) void k_reconstruct_fft(const T* __rest
         const int j = idx / kFftCols;
         const int m = m0 + c;
         if (m >= ny) continue;
-        const double2 v = z[(c >> 1) * M + j];
+        const double2 v = z[(c >> 1) * Mp + fft_pad(j)];
         out[static_cast<int64_t>(j) * ny + m] = (c & 1) ? v.y : v.x;
     }
 }
@@ -321,8 +348,9 @@ hipError_t launch_reconstruct(hipStream_t stream, const T* a, const T* b, int64_
     if (M >= 8 && M <= kFftMaxM && (M & (M - 1)) == 0) {
         const int logM = __builtin_ctz(static_cast<unsigned>(M));
         const int pairs = M <= 256 ? 8 : (M == 512 ? 4 : 2);
-        const size_t lds = (static_cast<size_t>(pairs) * M + M / 2) * sizeof(double2);
-        const int blocks = (ny + 2 * pairs - 1) / (2 * pairs);
+        const size_t lds = (static_cast<size_t>(pairs) * (M + M / 8) + M - 1) * sizeof(double2);
+        const int groups = (ny + 2 * pairs - 1) / (2 * pairs);
+        const int blocks = (groups + kXcds - 1) / kXcds * kXcds;   // whole rounds over the XCDs
         if (pairs == 8)
             hipLaunchKernelGGL((k_reconstruct_fft<T, 8>), dim3(blocks), dim3(kFftThreads), lds,
                                stream, a, b, ld, nx, ny, M, logM, out);

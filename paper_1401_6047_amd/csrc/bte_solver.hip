@@ -960,6 +960,39 @@ bte_status bte_state_observables_noalloc(const double* a, const double* b, int32
     return BTE_OK;
 }
 
+}  // extern "C"
+
+namespace {
+// Plain streaming copy, 16 bytes per access, four independent accesses in
+// flight per thread and turn of the grid-stride loop.
+__global__ __launch_bounds__(256) void k_stream_copy(const uint4* __restrict__ src,
+                                                     uint4* __restrict__ dst, size_t n16)
+{
+    const size_t stride = static_cast<size_t>(gridDim.x) * blockDim.x;
+    size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    for (; i + 3 * stride < n16; i += 4 * stride) {
+        const uint4 a = src[i], b = src[i + stride], c = src[i + 2 * stride],
+                    d = src[i + 3 * stride];
+        dst[i] = a;
+        dst[i + stride] = b;
+        dst[i + 2 * stride] = c;
+        dst[i + 3 * stride] = d;
+    }
+    for (; i < n16; i += stride) dst[i] = src[i];
+}
+
+hipError_t launch_stream_copy(const void* src, void* dst, size_t bytes, int blocks,
+                              hipStream_t st)
+{
+    hipLaunchKernelGGL(k_stream_copy, dim3(blocks), dim3(256), 0, st,
+                       static_cast<const uint4*>(src), static_cast<uint4*>(dst), bytes / 16);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+extern "C" {
+
 bte_status bte_stream_copy(const void* src, void* dst, size_t bytes, void* hip_stream)
 {
     if (!src || !dst) return fail(BTE_EINVAL, "src and dst must not be NULL");
@@ -972,8 +1005,8 @@ bte_status bte_stream_copy(const void* src, void* dst, size_t bytes, void* hip_s
     int dev = 0, cus = 256;
     HIP_TRY(hipGetDevice(&dev));
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    HIP_TRY(bte::launch_stream_copy(src, dst, bytes, 8 * std::max(cus, 1),
-                                    static_cast<hipStream_t>(hip_stream)));
+    HIP_TRY(launch_stream_copy(src, dst, bytes, 8 * std::max(cus, 1),
+                               static_cast<hipStream_t>(hip_stream)));
     return BTE_OK;
 }
 
