@@ -418,15 +418,19 @@ void bte_batch_destroy(bte_batch* b);
    harmonics per wave among the values that split n_x into 1 to 8 equal
    chunks, wavefronts per group 2, 4 or 8; wide schedule) by measurement.
    The cost per step of an instance depends only on its grid, so the tuner
-   runs a sample of up to 128 instances whose N_y values follow the batch's
-   share of cells, each with omega raised to periods of 400 steps and run for exactly
-   two periods (a fixed amount of work), once per candidate (after one
-   untimed run that captures the graphs), on `hip_stream`.  The library
-   allocates and frees the sample's device memory itself (a few GiB at most
-   for the largest grids).  With use_cache != 0 an earlier result for the same
-   (n_x, set of N_y values, precision) in this process is returned without
-   measuring.  *out receives the tuning; *cell_steps_per_s (may be NULL) the
-   sample's rate in cell-steps per second.  Errors as bte_batch_create. */
+   runs samples whose N_y values follow the batch's share of cells, each
+   instance with omega raised to periods of 400 steps and run for exactly
+   two periods (a fixed amount of work), on `hip_stream`, timing the second
+   of two runs (the first captures the graphs).  Stage one times every
+   candidate on up to 128 instances; when the batch is larger, stage two
+   re-times the three fastest on as many instances as the batch holds (at
+   most 4096) and keeps the fastest there.  The library allocates and frees
+   the samples' device memory itself (as much as the batch itself needs, at
+   most that of 4096 instances).  With use_cache != 0 an earlier result for
+   the same (n_x, set of N_y values, precision) in this process is returned
+   without measuring.  *out receives the tuning; *cell_steps_per_s (may be
+   NULL) the deciding sample's rate in cell-steps per second.  Errors as
+   bte_batch_create. */
 bte_status bte_batch_tune(const bte_batch_config* cfg, int32_t n, const bte_instance* inst,
                           void* hip_stream, int32_t use_cache, bte_batch_tuning* out,
                           double* cell_steps_per_s);
@@ -447,7 +451,6 @@ bte_status bte_run_periods(bte_solver* s, double tol, int32_t min_periods, int32
 /* Destroy the handle; frees what the library allocated.  NULL is a no-op. */
 void bte_destroy(bte_solver* s);
 
-/* Message of the last failing call on this thread ("" if none). */
 /* Plain device copy of `bytes` from src to dst (both 16-byte aligned, not
    overlapping, bytes a multiple of 16), queued on `hip_stream`.  Not part of
    the method: the read+write streaming rate it reaches is the practical HBM
@@ -456,6 +459,7 @@ void bte_destroy(bte_solver* s);
    sizes. */
 bte_status bte_stream_copy(const void* src, void* dst, size_t bytes, void* hip_stream);
 
+/* Message of the last failing call on this thread ("" if none). */
 const char* bte_last_error(void);
 
 /* Library version string. */

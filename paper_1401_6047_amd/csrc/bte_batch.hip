@@ -1175,13 +1175,19 @@ bte_status bte_batch_get_tuning(const bte_batch* b, bte_batch_tuning* t)
 
 // ---- sweep autotuner ------------------------------------------------------------
 // The per-step cost of an instance depends only on its grid (N_x shared, its
-// own N_y) and the tile shape, not on its fields: the tuner runs a sample of
+// own N_y) and the tile shape, not on its fields: the tuner runs samples of
 // the batch whose N_y values follow the batch's share of cells, with omega
 // raised so that every instance runs exactly `kTunePeriods` periods of
 // `kTunePeriodSteps` steps (a fixed, known amount of work), through the wide
-// schedule, and times it for each candidate shape.
+// schedule, and times them.  Stage one ranks every candidate on a small
+// sample; stage two re-times the best few on a sample as large as the batch
+// (up to kTuneLarge instances), since a shape's rate can change once the
+// passes carry thousands of instances (ties at a hundred instances have come
+// apart by a tenth at four thousand).
 namespace {
-constexpr int kTuneSample = 128;        // instances in the tuning sample (at most)
+constexpr int kTuneSample = 128;        // instances in the stage-one sample (at most)
+constexpr int kTuneLarge = 4096;        // instances in the stage-two sample (at most)
+constexpr int kTuneFinalists = 3;       // candidates re-timed in stage two
 constexpr int kTunePeriodSteps = 400;   // steps per period of a sample instance
 constexpr int kTunePeriods = 2;
 
@@ -1209,6 +1215,52 @@ std::vector<int> balanced_rows(int nx, int rmax)
     }
     return r;
 }
+
+// m sample instances (about; at least one per class): each N_y class in
+// proportion to its share of the batch's cells, with a representative's
+// fields and omega set for periods of kTunePeriodSteps steps.
+std::vector<bte_instance> tune_sample(const bte_batch_config* cfg, int n, const bte_instance* inst,
+                                      const std::map<int, double>& cells, int m)
+{
+    double total = 0.0;
+    for (const auto& kv : cells) total += kv.second;
+    std::vector<bte_instance> sample;
+    for (const auto& kv : cells) {
+        const int k = std::max(1, static_cast<int>(std::lround(m * kv.second / total)));
+        const bte_instance* rep = nullptr;
+        for (int i = 0; i < n && !rep; ++i)
+            if (inst[i].n_y == kv.first) rep = &inst[i];
+        bte_instance x = *rep;
+        x.omega = 2.0 * kPi / (kTunePeriodSteps * cfg->dt);
+        for (int j = 0; j < k; ++j) sample.push_back(x);
+    }
+    return sample;
+}
+
+// Cell-steps per second of the sample under tuning t (the second of two runs:
+// the first captures the graphs), or an error status.
+bte_status time_sample(const bte_batch_config& c, const std::vector<bte_instance>& sample,
+                       const bte_batch_tuning& t, void* hip_stream, double* rate)
+{
+    double work = 0.0;
+    for (const bte_instance& x : sample)
+        work += static_cast<double>(x.n_y) * c.n_x * kTunePeriods * kTunePeriodSteps;
+    bte_batch* b = nullptr;
+    bte_status st = bte_batch_create(&c, static_cast<int32_t>(sample.size()), sample.data(), &t,
+                                     nullptr, 0, hip_stream, &b);
+    if (st != BTE_OK) return st;
+    double secs = 1e300;
+    for (int rep = 0; rep < 2 && st == BTE_OK; ++rep) {
+        const auto t0 = std::chrono::steady_clock::now();
+        st = bte_batch_run(b);
+        const auto t1 = std::chrono::steady_clock::now();
+        secs = std::chrono::duration<double>(t1 - t0).count();
+    }
+    bte_batch_destroy(b);
+    if (st != BTE_OK) return st;
+    *rate = work / secs;
+    return BTE_OK;
+}
 }  // namespace
 
 extern "C" {
@@ -1235,28 +1287,9 @@ bte_status bte_batch_tune(const bte_batch_config* cfg, int32_t n, const bte_inst
             return BTE_OK;
         }
     }
-    // the sample: N_y classes in proportion to their cells, at least one each
-    double total = 0.0;
-    for (const auto& kv : cells) total += kv.second;
-    const int m = std::min<int>(n, kTuneSample);
-    std::vector<bte_instance> sample;
-    for (const auto& kv : cells) {
-        const int k = std::max(1, static_cast<int>(std::lround(m * kv.second / total)));
-        // a representative instance of the class (its fields do not change
-        // the cost), with omega set for periods of kTunePeriodSteps steps
-        const bte_instance* rep = nullptr;
-        for (int i = 0; i < n && !rep; ++i)
-            if (inst[i].n_y == kv.first) rep = &inst[i];
-        bte_instance x = *rep;
-        x.omega = 2.0 * kPi / (kTunePeriodSteps * cfg->dt);
-        for (int j = 0; j < k; ++j) sample.push_back(x);
-    }
     bte_batch_config c = *cfg;
     c.min_periods = c.max_periods = kTunePeriods;
     c.confirm = 1;
-    double work = 0.0;
-    for (const bte_instance& x : sample)
-        work += static_cast<double>(x.n_y) * c.n_x * kTunePeriods * kTunePeriodSteps;
 
     std::vector<bte_batch_tuning> cand;
     for (int form : {BTE_KERNEL_FUSED2, BTE_KERNEL_FUSED})
@@ -1270,27 +1303,35 @@ bte_status bte_batch_tune(const bte_batch_config* cfg, int32_t n, const bte_inst
                 t.schedule = BTE_BATCH_WIDE;
                 cand.push_back(t);
             }
-    bte_batch_tuning best{};
-    double best_rate = -1.0;
-    const int ns = static_cast<int>(sample.size());
-    for (const bte_batch_tuning& t : cand) {
-        bte_batch* b = nullptr;
-        st = bte_batch_create(&c, ns, sample.data(), &t, nullptr, 0, hip_stream, &b);
+    // stage one: every candidate on the small sample
+    const int m1 = std::min<int>(n, kTuneSample);
+    const std::vector<bte_instance> small = tune_sample(cfg, n, inst, cells, m1);
+    std::vector<std::pair<double, int>> ranked;      // (rate, candidate), best first
+    for (int i = 0; i < static_cast<int>(cand.size()); ++i) {
+        double rate = 0.0;
+        st = time_sample(c, small, cand[i], hip_stream, &rate);
         if (st != BTE_OK) return st;
-        double secs = 1e300;
-        // the first run includes the graph capture; time the second
-        for (int rep = 0; rep < 2 && st == BTE_OK; ++rep) {
-            const auto t0 = std::chrono::steady_clock::now();
-            st = bte_batch_run(b);
-            const auto t1 = std::chrono::steady_clock::now();
-            secs = std::chrono::duration<double>(t1 - t0).count();
-        }
-        bte_batch_destroy(b);
-        if (st != BTE_OK) return st;
-        const double rate = work / secs;
-        if (rate > best_rate) {
-            best_rate = rate;
-            best = t;
+        ranked.push_back({rate, i});
+    }
+    std::stable_sort(ranked.begin(), ranked.end(),
+                     [](const std::pair<double, int>& a, const std::pair<double, int>& b) { return a.first > b.first; });
+    bte_batch_tuning best = cand[ranked[0].second];
+    double best_rate = ranked[0].first;
+    // stage two: the finalists on a sample as large as the batch
+    const int m2 = std::min<int>(n, kTuneLarge);
+    if (m2 > m1) {
+        const std::vector<bte_instance> large = tune_sample(cfg, n, inst, cells, m2);
+        best_rate = -1.0;
+        const int f = std::min<int>(kTuneFinalists, static_cast<int>(ranked.size()));
+        for (int j = 0; j < f; ++j) {
+            const bte_batch_tuning& t = cand[ranked[j].second];
+            double rate = 0.0;
+            st = time_sample(c, large, t, hip_stream, &rate);
+            if (st != BTE_OK) return st;
+            if (rate > best_rate) {
+                best_rate = rate;
+                best = t;
+            }
         }
     }
     {

@@ -301,3 +301,30 @@ def test_sweep_autotuner_picks_a_legal_shape_and_caches_it(bte, small, tmp_path)
     b2 = bte.Batch(cfg, small, autotune=True, tuning_cache=path)
     assert b2.tune_rate == pytest.approx(rate)
     b2.close()
+
+
+def test_sweep_autotuner_second_stage_on_a_batch_larger_than_its_sample(bte):
+    """A batch of more than 128 instances takes the tuner's second stage (the
+    three fastest candidates re-timed on a sample as large as the batch): the
+    pick is still a legal tile, is cached, and gives the default tile's FP64
+    results instance by instance."""
+    inst = W.small_sweep_draws(300, seed=20240611)
+    w0 = inst[0]
+    cfg = bte.make_batch_config(w0.nx, w0.phiy_min, w0.phiy_max, w0.dt, precision=0, tol=1e-6,
+                                min_periods=2, max_periods=60)
+    t, rate = bte.bte_batch_tune(cfg, inst, use_cache=False)
+    print(f"tuned (300 instances): kernel {t.kernel} R{t.rows_per_wave} W{t.waves_per_group}, "
+          f"{rate / 1e9:.1f} G cell-steps/s", flush=True)
+    assert t.kernel in (bte.BTE_KERNEL_FUSED, bte.BTE_KERNEL_FUSED2)
+    assert t.waves_per_group in (2, 4, 8) and t.schedule == bte.BTE_BATCH_WIDE
+    assert any(t.rows_per_wave == -(-w0.nx // c) for c in range(1, 9)) and rate > 0
+    t2, rate2 = bte.bte_batch_tune(cfg, inst)
+    assert (t2.kernel, t2.rows_per_wave, t2.waves_per_group, rate2) == \
+        (t.kernel, t.rows_per_wave, t.waves_per_group, rate)
+    ref = run_batch(bte, inst, precision=0)
+    b = bte.Batch(cfg, inst, tuning=t)
+    b.run(log=None)
+    got = b.results()
+    b.close()
+    for x, y in zip(got, ref):
+        assert x["absorption"] == y["absorption"] and x["periods"] == y["periods"]
