@@ -424,9 +424,9 @@ void bte_batch_destroy(bte_batch* b);
    of two runs (the first captures the graphs).  Stage one times every
    candidate on up to 128 instances; when the batch is larger, stage two
    re-times the three fastest on as many instances as the batch holds (at
-   most 4096) and keeps the fastest there.  The library allocates and frees
-   the samples' device memory itself (as much as the batch itself needs, at
-   most that of 4096 instances).  With use_cache != 0 an earlier result for
+   most 4096) and keeps the fastest there.  Neither sample takes more state
+   slots than fit in 64 GiB (the wide schedule's default budget).  The
+   library allocates and frees the samples' device memory itself.  With use_cache != 0 an earlier result for
    the same (n_x, set of N_y values, precision) in this process is returned
    without measuring.  *out receives the tuning; *cell_steps_per_s (may be
    NULL) the deciding sample's rate in cell-steps per second.  Errors as

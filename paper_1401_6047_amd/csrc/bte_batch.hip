@@ -1303,8 +1303,11 @@ bte_status bte_batch_tune(const bte_batch_config* cfg, int32_t n, const bte_inst
                 t.schedule = BTE_BATCH_WIDE;
                 cand.push_back(t);
             }
+    // the samples' state slots stay within the wide schedule's default budget
+    const double slot = static_cast<double>(batch_layout(c, 1, ny_max, cand[0]).slot_bytes);
+    const int cap = std::max(1, static_cast<int>(std::min(kWideDefaultBytes / slot, 1e9)));
     // stage one: every candidate on the small sample
-    const int m1 = std::min<int>(n, kTuneSample);
+    const int m1 = std::min({n, kTuneSample, cap});
     const std::vector<bte_instance> small = tune_sample(cfg, n, inst, cells, m1);
     std::vector<std::pair<double, int>> ranked;      // (rate, candidate), best first
     for (int i = 0; i < static_cast<int>(cand.size()); ++i) {
@@ -1318,7 +1321,7 @@ bte_status bte_batch_tune(const bte_batch_config* cfg, int32_t n, const bte_inst
     bte_batch_tuning best = cand[ranked[0].second];
     double best_rate = ranked[0].first;
     // stage two: the finalists on a sample as large as the batch
-    const int m2 = std::min<int>(n, kTuneLarge);
+    const int m2 = std::min({n, kTuneLarge, cap});
     if (m2 > m1) {
         const std::vector<bte_instance> large = tune_sample(cfg, n, inst, cells, m2);
         best_rate = -1.0;
