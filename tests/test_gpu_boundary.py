@@ -219,9 +219,9 @@ def test_state_observables_rejects_bad_arguments(bte):
 
 
 def test_stream_copy_copies_and_validates(bte):
-    """bte_stream_copy (the measurement copy): exact bytes for sizes with and
-    without a remainder of its four-way unrolled loop; rejects overlap and
-    misalignment."""
+    """bte_stream_copy (the measurement copy): exact bytes for one unit, for
+    whole 16 KiB runs plus a partial run, and for whole runs only; rejects
+    overlap and misalignment."""
     import torch
     for n in (16, 4096 * 16 + 48, 3 << 20):
         src = torch.randint(0, 255, (n,), dtype=torch.uint8, device="cuda")
