@@ -627,9 +627,17 @@ def main():
     line["roofline"]["practical_peak_GBs"] = practical
     line["roofline"]["frac_of_practical"] = main_run["achieved_GBs"] / practical
     if args.copy_mib > 0:
-        # a plain copy of known size for scaling the HBM traffic counters of
-        # the step kernel (k_stream_copy, 5 runs)
-        stream_copy_rate(bte, torch, mib=args.copy_mib, reps=5)
+        # a plain device copy of known size (torch's copy: temporal 128-byte
+        # reads like the step kernels' row loads) for scaling the HBM traffic
+        # counters of the step kernel; the FETCH_SIZE formula counts such
+        # reads at half their size on this chip
+        n = args.copy_mib << 20
+        src = torch.ones(n // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
         line["copy_probe_mib"] = args.copy_mib
     if args.sweep > 0:
         line["sweep"] = sweep_bench(bte, torch, args.sweep, min(args.sweep_fp64, args.sweep),

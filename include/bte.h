@@ -453,9 +453,9 @@ void bte_destroy(bte_solver* s);
 
 /* Plain device copy of `bytes` from src to dst (both 16-byte aligned, not
    overlapping, bytes a multiple of 16), queued on `hip_stream`.  Not part of
-   the method: the read+write streaming rate it reaches is the practical HBM
-   ceiling the step kernels are measured against, and the copy of known size
-   that calibrates the traffic counters.  BTE_EINVAL for bad pointers or
+   the method: the read+write streaming rate it reaches (one 16 KiB run per
+   workgroup, non-temporal loads and stores) is the practical HBM ceiling the
+   step kernels are measured against.  BTE_EINVAL for bad pointers or
    sizes. */
 bte_status bte_stream_copy(const void* src, void* dst, size_t bytes, void* hip_stream);
 
