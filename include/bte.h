@@ -427,7 +427,8 @@ void bte_batch_destroy(bte_batch* b);
    most 4096) and keeps the fastest there.  Neither sample takes more state
    slots than fit in 64 GiB (the wide schedule's default budget).  The
    library allocates and frees the samples' device memory itself.  With use_cache != 0 an earlier result for
-   the same (n_x, set of N_y values, precision) in this process is returned
+   the same (n_x, set of N_y values, precision, batch-size class: the
+   smallest power of two >= min(n, 4096)) in this process is returned
    without measuring.  *out receives the tuning; *cell_steps_per_s (may be
    NULL) the deciding sample's rate in cell-steps per second.  Errors as
    bte_batch_create. */

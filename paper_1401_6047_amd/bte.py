@@ -552,9 +552,14 @@ def bte_batch_tune(cfg: bte_batch_config, instances, stream_ptr=0, use_cache=Tru
 
 
 def tuning_cache_key(cfg: bte_batch_config, instances) -> str:
-    """Key of a batch tuning: harmonics, precision and the set of N_y values."""
+    """Key of a batch tuning: harmonics, precision, the batch-size class (the
+    smallest power of two at or above min(n, 4096)) and the set of N_y
+    values, as the library's own cache keys it."""
     nys = sorted({int(w.ny) for w in instances})
-    return f"nx{cfg.n_x}-p{cfg.precision}-ny" + ",".join(str(v) for v in nys)
+    cls = 1
+    while cls < min(len(instances), 4096):
+        cls *= 2
+    return f"nx{cfg.n_x}-p{cfg.precision}-n{cls}-ny" + ",".join(str(v) for v in nys)
 
 
 class Batch:

@@ -1193,14 +1193,23 @@ constexpr int kTunePeriods = 2;
 
 struct TuneKey {
     int n_x, precision;
+    int size_class;                     // smallest power of two >= min(n, kTuneLarge)
     std::vector<int> ny;                // distinct N_y values of the batch, sorted
     bool operator<(const TuneKey& o) const
     {
         if (n_x != o.n_x) return n_x < o.n_x;
         if (precision != o.precision) return precision < o.precision;
+        if (size_class != o.size_class) return size_class < o.size_class;
         return ny < o.ny;
     }
 };
+
+int size_class(int n)
+{
+    int c = 1;
+    while (c < std::min(n, kTuneLarge)) c <<= 1;
+    return c;
+}
 std::mutex g_tune_mu;
 std::map<TuneKey, std::pair<bte_batch_tuning, double>> g_tune_cache;
 
@@ -1276,7 +1285,7 @@ bte_status bte_batch_tune(const bte_batch_config* cfg, int32_t n, const bte_inst
     // cells per distinct N_y, and the cache key
     std::map<int, double> cells;
     for (int i = 0; i < n; ++i) cells[inst[i].n_y] += static_cast<double>(inst[i].n_y) * cfg->n_x;
-    TuneKey key{cfg->n_x, cfg->precision, {}};
+    TuneKey key{cfg->n_x, cfg->precision, size_class(n), {}};
     for (const auto& kv : cells) key.ny.push_back(kv.first);
     if (use_cache) {
         std::lock_guard<std::mutex> lock(g_tune_mu);
