@@ -83,6 +83,13 @@ def parse():
                     help="also time the direct-sum kernel at this many samples (0: skip)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
+    ap.add_argument("--batch-probe", type=int, default=0,
+                    help="instead of timing the solver: run a fixed-work batch of this many "
+                         "sweep-grid instances (two periods of 400 steps each, wide schedule, "
+                         "FP32 bulk) twice and report the second run; for profiling the "
+                         "batch kernels")
+    ap.add_argument("--probe-rows", type=int, default=43)
+    ap.add_argument("--probe-waves", type=int, default=4)
     ap.add_argument("--full-run", choices=("fp64", "fp32"), default=None,
                     help="instead of timing: integrate the workload from f0 over "
                          "--full-periods ac periods in this precision and report the "
@@ -401,6 +408,60 @@ def cpu_baseline(w, sample_steps):
                                      f"{secs1:.1f} s, 1 thread"}}
 
 
+def calibration_copy(torch, mib):
+    """A plain device copy of known size (torch's copy: temporal 128-byte reads
+    like the step kernels' row loads), five times, for scaling the HBM
+    traffic counters of the kernels profiled in the same run; the FETCH_SIZE
+    formula counts such reads at half their size on this chip."""
+    n = mib << 20
+    src = torch.ones(n // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+
+
+def batch_probe(bte, torch, n, rows, waves):
+    """A fixed amount of batched work: n instances of the sweep's grids (N_y
+    classes in proportion to their cells, as the sweep autotuner samples
+    them) with omega set for periods of 400 steps, each run for exactly two
+    periods in the wide schedule with the two-step FP32-bulk kernel.  The
+    first run captures the graphs; the second is timed.  Every pass advances
+    every instance two steps, so a pass moves 32 B per cell (four FP32
+    planes read and written once)."""
+    from dataclasses import replace
+    from paper_1401_6047_amd import workloads as W
+    draws = W.sweep_draws(4096)
+    nx, phi, dt = draws[0].nx, draws[0].phiy_max, draws[0].dt
+    cells = {}
+    for w in draws:
+        cells[w.ny] = cells.get(w.ny, 0) + w.ny * nx
+    total = sum(cells.values())
+    rep = {w.ny: w for w in draws}
+    sample = []
+    for ny, c in sorted(cells.items()):
+        sample += [replace(rep[ny], omega=2.0 * math.pi / (400 * dt))] * max(1, round(n * c / total))
+    cfg = bte.make_batch_config(nx, -phi, phi, dt, precision=bte.BTE_FP32_BULK, tol=1e-6,
+                                min_periods=2, max_periods=2, confirm=1)
+    t = bte.bte_batch_tuning(bte.BTE_KERNEL_FUSED2, rows, waves, 0, bte.BTE_BATCH_WIDE)
+    b = bte.Batch(cfg, sample, tuning=t)
+    b.run(log=None)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.run(log=None)
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    res = b.results()
+    b.close()
+    cell_count = sum(w.ny * nx for w in sample)
+    return {"instances": len(sample), "cells": cell_count, "passes": 400,
+            "bytes_per_pass": 32 * cell_count, "wall_s": secs,
+            "cell_steps_per_s": cell_count * 800 / secs,
+            "tile": {"kernel": 2, "rows_per_wave": rows, "waves_per_group": waves},
+            "all_ran_two_periods": all(r["periods"] == 2 for r in res)}
+
+
 def stratified(draws, per_class):
     """Indices of the first `per_class` draws of each temperature class."""
     idx = []
@@ -556,6 +617,14 @@ def main():
     from paper_1401_6047_amd import workloads as W
 
     w = W.WORKLOADS[args.workload]
+    if args.batch_probe > 0:
+        line = {"batch_probe": batch_probe(bte, torch, args.batch_probe, args.probe_rows,
+                                           args.probe_waves)}
+        if args.copy_mib > 0:
+            calibration_copy(torch, args.copy_mib)
+            line["copy_probe_mib"] = args.copy_mib
+        print(json.dumps(line), flush=True)
+        return
     if args.full_run:
         full_run(bte, torch, w, 1 if args.full_run == "fp32" else 0, args)
         return
@@ -627,17 +696,7 @@ def main():
     line["roofline"]["practical_peak_GBs"] = practical
     line["roofline"]["frac_of_practical"] = main_run["achieved_GBs"] / practical
     if args.copy_mib > 0:
-        # a plain device copy of known size (torch's copy: temporal 128-byte
-        # reads like the step kernels' row loads) for scaling the HBM traffic
-        # counters of the step kernel; the FETCH_SIZE formula counts such
-        # reads at half their size on this chip
-        n = args.copy_mib << 20
-        src = torch.ones(n // 8, dtype=torch.float64, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(5):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+        calibration_copy(torch, args.copy_mib)
         line["copy_probe_mib"] = args.copy_mib
     if args.sweep > 0:
         line["sweep"] = sweep_bench(bte, torch, args.sweep, min(args.sweep_fp64, args.sweep),
