@@ -673,8 +673,9 @@ def main():
                      "kernel": main_run["kernel"],
                      "valu_busy": counter_valu_busy(main_run["kernel"], args.precision,
                                                     main_run["tuning"]),
-                     "limiter": "VALU instruction issue (SQ counters); the HBM traffic "
-                                "is hidden under it",
+                     "limiter": "VALU instruction issue of two wavefronts per SIMD "
+                                "(SQ counters, wavefront timeline); the HBM traffic is "
+                                "hidden under it",
                      "steps_per_launch": main_run["steps_per_launch"],
                      "bytes_per_launch": main_run["bytes_per_launch"],
                      "avg_launch_us": main_run["avg_launch_us"]},

@@ -232,7 +232,26 @@ struct TileEnv {
     int R;                    // harmonics per wave
     int nchunks;              // ceil(nx / R)
     int cgroup;               // two-step tiles: phi_y strips per column group (see fused2_tile)
+    bool even_progress;       // the whole launch is resident at once (see march_priority)
 };
+
+// Issue priority by progress through the march.  Two wavefronts sharing a
+// SIMD otherwise run oldest-first: one finishes about as fast as if it were
+// alone, and the other then runs its remainder alone, at the lower issue rate
+// of a single wavefront.  Lowering a wavefront's priority as it advances (four
+// levels over its iterations) keeps the progress of the wavefronts on a SIMD
+// even, so that they overlap for most of the launch.  Only used when every
+// wavefront of the launch is resident at once (with more wavefronts than
+// slots it would hold back the wavefronts that free a slot for the next) and
+// they fill a good part of the device.
+__device__ __forceinline__ void march_priority(int i, int iters)
+{
+    const int lvl = (i * 4) / iters;
+    if (lvl == 0) __builtin_amdgcn_s_setprio(3);
+    else if (lvl == 1) __builtin_amdgcn_s_setprio(2);
+    else if (lvl == 2) __builtin_amdgcn_s_setprio(1);
+    else __builtin_amdgcn_s_setprio(0);
+}
 
 // Tiles of the two-step kernel for a grid of `ncol` phi_y strips, in column
 // groups of `cgroup` strips (the last group padded): the kernels launch or
@@ -682,6 +701,7 @@ __device__ __forceinline__ void fused2_tile(const TileEnv<T>& A, int tile, doubl
         // memory pipeline.
         __builtin_amdgcn_s_waitcnt(0);
         for (int i = 0; i < iters; i += 6) {
+            if (A.even_progress) march_priority(i, iters);
             const int j = jfirst + D * i;
             iter(j, S[0], S[1], S[2]);
             iter(j + D, S[1], S[2], S[0]);
@@ -949,6 +969,7 @@ __device__ __forceinline__ void fused3_tile(const TileEnv<T>& A, int tile, doubl
         const int iters = (jhi - jlo + 1 + 5) / 6 * 6;
         __builtin_amdgcn_s_waitcnt(0);
         for (int i = 0; i < iters; i += 6) {
+            if (A.even_progress) march_priority(i, iters);
             const int j = jfirst + D * i;
             iter(j, S[0], S[1], S[2]);
             iter(j + D, S[1], S[2], S[0]);
