@@ -135,7 +135,9 @@ typedef struct {
 typedef struct bte_solver bte_solver;
 
 /* Device bytes a solver with this grid and parameters needs.  Validates the
-   arguments the same way bte_create does. */
+   arguments the same way bte_create does (BTE_EINVAL also for a grid whose
+   set of four state planes would reach 2 GiB: the step kernels address a
+   set with 32-bit byte offsets). */
 bte_status bte_workspace_bytes(const bte_grid* grid, const bte_params* params, size_t* bytes);
 
 /* Create a solver: lay out the workspace, set the whole grid to the

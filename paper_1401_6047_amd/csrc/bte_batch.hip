@@ -978,8 +978,8 @@ bte_status bte_batch_create(const bte_batch_config* cfg, int32_t n, const bte_in
     if (st != BTE_OK) return st;
     const bte_batch_tuning t = tuning ? *tuning : default_tuning_for(*cfg, n, ny_max);
     BatchLayout L = batch_layout(*cfg, n, ny_max, t);
-    if (static_cast<double>(L.plane_bytes) >= 2147483648.0)
-        return bfail(BTE_EINVAL, "grid too large: one state plane must stay below 2 GiB");
+    if (4.0 * static_cast<double>(L.plane_bytes) >= 2147483648.0)
+        return bfail(BTE_EINVAL, "grid too large: a set of four state planes must stay below 2 GiB");
     if (workspace && workspace_bytes < L.total)
         return bfail(BTE_ENOMEM, "workspace too small: need " + std::to_string(L.total) + " bytes");
     if (workspace && reinterpret_cast<uintptr_t>(workspace) % kAlign)

@@ -128,7 +128,8 @@ __device__ __forceinline__ int wave_tile()
 // Row access through a buffer resource: the row offset is a scalar (SGPR)
 // operand and the lane's column a 32-bit VGPR offset, so no vector address
 // arithmetic is spent per access.  The descriptor's record count is the
-// plane's size: an access outside the plane reads 0 and a store is dropped.
+// extent it covers (a plane, or the four planes of a state set): an access
+// outside it reads 0 and a store is dropped.
 constexpr int kBufferWord3 = 0x00020000;   // gfx9 raw buffer, no format conversion
 
 // ---- FP32 storage with stochastic rounding -------------------------------------
@@ -179,16 +180,17 @@ struct RowAddr {
     uint32_t row_bytes;   // ld * sizeof(T)
     uint32_t col_bytes;   // (m + kPadCols) * sizeof(T), per lane
     uint32_t seed;        // stochastic-rounding seed of this plane and launch (FP32 only)
-    __device__ __forceinline__ RowAddr(const T* base, uint32_t plane_bytes, uint32_t rb, uint32_t cb,
-                                       uint32_t sd = 0)
+    uint32_t poff;        // byte offset of this plane from the descriptor's base
+    __device__ __forceinline__ RowAddr(const T* base, uint32_t bytes, uint32_t rb, uint32_t cb,
+                                       uint32_t sd = 0, uint32_t po = 0)
         : rsrc(__builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(base), static_cast<short>(0),
-                                                 static_cast<int>(plane_bytes), kBufferWord3)),
-          row_bytes(rb), col_bytes(cb), seed(sd)
+                                                 static_cast<int>(bytes), kBufferWord3)),
+          row_bytes(rb), col_bytes(cb), seed(sd), poff(po)
     {
     }
     __device__ __forceinline__ int soff(int j) const
     {
-        return static_cast<int>(static_cast<uint32_t>(j + kPadRows) * row_bytes);
+        return static_cast<int>(static_cast<uint32_t>(j + kPadRows) * row_bytes + poff);
     }
     __device__ __forceinline__ double load(int j) const
     {
@@ -207,12 +209,24 @@ struct RowAddr {
             __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, x), rsrc, col_bytes, soff(j), 0);
         } else {
             using V = decltype(__builtin_amdgcn_raw_buffer_load_b32(rsrc, 0u, 0, 0));
-            const uint32_t cell = static_cast<uint32_t>(soff(j)) + col_bytes;
+            const uint32_t cell = static_cast<uint32_t>(soff(j)) - poff + col_bytes;
             const float f = round_stochastic(x, mix32(seed ^ cell));
             __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(V, f), rsrc, col_bytes, soff(j), 0);
         }
     }
 };
+
+// The four planes of a state set lie at one stride, in the order a_h, b_h,
+// a_f, b_f (both the single-instance workspace and the batch slots are laid
+// out so, and the launchers check it): one buffer descriptor then covers the
+// set and a plane is a fixed byte offset into it, which leaves the march far
+// fewer scalar registers to hold than a descriptor per plane.
+template <typename T>
+__device__ __forceinline__ uint32_t plane_stride(const Planes<T>& P)
+{
+    return static_cast<uint32_t>(reinterpret_cast<const char*>(P.b_h) -
+                                 reinterpret_cast<const char*>(P.a_h));
+}
 
 // Everything a tile of a step kernel reads besides its tile index.  The
 // single-instance kernels fill it from the device control block; the batched
@@ -331,14 +345,15 @@ __device__ __forceinline__ void fused_tile(const TileEnv<T>& A, int tile)
     const uint32_t rb = static_cast<uint32_t>(cs.ld) * sizeof(T);
     const uint32_t cb = static_cast<uint32_t>(m + kPadCols) * sizeof(T);
     const uint32_t pb = static_cast<uint32_t>(cs.nx + 2 * kPadRows) * rb;
-    const RowAddr<T> aHs(A.src.a_h, pb, rb, cb);
-    const RowAddr<T> bHs(A.src.b_h, pb, rb, cb);
-    const RowAddr<T> aFs(A.src.a_f, pb, rb, cb);
-    const RowAddr<T> bFs(A.src.b_f, pb, rb, cb);
-    const RowAddr<T> aHd(A.dst.a_h, pb, rb, cb, plane_seed(k, 0 + A.salt));
-    const RowAddr<T> bHd(A.dst.b_h, pb, rb, cb, plane_seed(k, 1 + A.salt));
-    const RowAddr<T> aFd(A.dst.a_f, pb, rb, cb, plane_seed(k, 2 + A.salt));
-    const RowAddr<T> bFd(A.dst.b_f, pb, rb, cb, plane_seed(k, 3 + A.salt));
+    const uint32_t ss = plane_stride(A.src), sd = plane_stride(A.dst);
+    const RowAddr<T> aHs(A.src.a_h, 3 * ss + pb, rb, cb, 0, 0);
+    const RowAddr<T> bHs(A.src.a_h, 3 * ss + pb, rb, cb, 0, ss);
+    const RowAddr<T> aFs(A.src.a_h, 3 * ss + pb, rb, cb, 0, 2 * ss);
+    const RowAddr<T> bFs(A.src.a_h, 3 * ss + pb, rb, cb, 0, 3 * ss);
+    const RowAddr<T> aHd(A.dst.a_h, 3 * sd + pb, rb, cb, plane_seed(k, 0 + A.salt), 0);
+    const RowAddr<T> bHd(A.dst.a_h, 3 * sd + pb, rb, cb, plane_seed(k, 1 + A.salt), sd);
+    const RowAddr<T> aFd(A.dst.a_h, 3 * sd + pb, rb, cb, plane_seed(k, 2 + A.salt), 2 * sd);
+    const RowAddr<T> bFd(A.dst.a_h, 3 * sd + pb, rb, cb, plane_seed(k, 3 + A.salt), 3 * sd);
 
     // Sliding window over harmonics.  Iteration j computes the new whole grid
     // at harmonic j (needs old fractional rows j-1, j+1) and the new
@@ -533,14 +548,15 @@ __device__ __forceinline__ void fused2_tile(const TileEnv<T>& A, int tile, doubl
     const uint32_t rb = static_cast<uint32_t>(cs.ld) * sizeof(T);
     const uint32_t cb = static_cast<uint32_t>(m + kPadCols) * sizeof(T);
     const uint32_t pb = static_cast<uint32_t>(cs.nx + 2 * kPadRows) * rb;
-    const RowAddr<T> aHs(A.src.a_h, pb, rb, cb);
-    const RowAddr<T> bHs(A.src.b_h, pb, rb, cb);
-    const RowAddr<T> aFs(A.src.a_f, pb, rb, cb);
-    const RowAddr<T> bFs(A.src.b_f, pb, rb, cb);
-    const RowAddr<T> aHd(A.dst.a_h, pb, rb, cb, plane_seed(k, 0 + A.salt));
-    const RowAddr<T> bHd(A.dst.b_h, pb, rb, cb, plane_seed(k, 1 + A.salt));
-    const RowAddr<T> aFd(A.dst.a_f, pb, rb, cb, plane_seed(k, 2 + A.salt));
-    const RowAddr<T> bFd(A.dst.b_f, pb, rb, cb, plane_seed(k, 3 + A.salt));
+    const uint32_t ss = plane_stride(A.src), sd = plane_stride(A.dst);
+    const RowAddr<T> aHs(A.src.a_h, 3 * ss + pb, rb, cb, 0, 0);
+    const RowAddr<T> bHs(A.src.a_h, 3 * ss + pb, rb, cb, 0, ss);
+    const RowAddr<T> aFs(A.src.a_h, 3 * ss + pb, rb, cb, 0, 2 * ss);
+    const RowAddr<T> bFs(A.src.a_h, 3 * ss + pb, rb, cb, 0, 3 * ss);
+    const RowAddr<T> aHd(A.dst.a_h, 3 * sd + pb, rb, cb, plane_seed(k, 0 + A.salt), 0);
+    const RowAddr<T> bHd(A.dst.a_h, 3 * sd + pb, rb, cb, plane_seed(k, 1 + A.salt), sd);
+    const RowAddr<T> aFd(A.dst.a_h, 3 * sd + pb, rb, cb, plane_seed(k, 2 + A.salt), 2 * sd);
+    const RowAddr<T> bFd(A.dst.a_h, 3 * sd + pb, rb, cb, plane_seed(k, 3 + A.salt), 3 * sd);
 
     const int jlo = r0 - 3;                           // first W1 row
     const int jhi = r1 + 2;                           // last W1 row
@@ -792,14 +808,15 @@ __device__ __forceinline__ void fused3_tile(const TileEnv<T>& A, int tile, doubl
     // zero border: they read its outermost (zero) column
     const uint32_t cb = static_cast<uint32_t>(max(m, -kPadCols) + kPadCols) * sizeof(T);
     const uint32_t pb = static_cast<uint32_t>(cs.nx + 2 * kPadRows) * rb;
-    const RowAddr<T> aHs(A.src.a_h, pb, rb, cb);
-    const RowAddr<T> bHs(A.src.b_h, pb, rb, cb);
-    const RowAddr<T> aFs(A.src.a_f, pb, rb, cb);
-    const RowAddr<T> bFs(A.src.b_f, pb, rb, cb);
-    const RowAddr<T> aHd(A.dst.a_h, pb, rb, cb, plane_seed(k, 0 + A.salt));
-    const RowAddr<T> bHd(A.dst.b_h, pb, rb, cb, plane_seed(k, 1 + A.salt));
-    const RowAddr<T> aFd(A.dst.a_f, pb, rb, cb, plane_seed(k, 2 + A.salt));
-    const RowAddr<T> bFd(A.dst.b_f, pb, rb, cb, plane_seed(k, 3 + A.salt));
+    const uint32_t ss = plane_stride(A.src), sd = plane_stride(A.dst);
+    const RowAddr<T> aHs(A.src.a_h, 3 * ss + pb, rb, cb, 0, 0);
+    const RowAddr<T> bHs(A.src.a_h, 3 * ss + pb, rb, cb, 0, ss);
+    const RowAddr<T> aFs(A.src.a_h, 3 * ss + pb, rb, cb, 0, 2 * ss);
+    const RowAddr<T> bFs(A.src.a_h, 3 * ss + pb, rb, cb, 0, 3 * ss);
+    const RowAddr<T> aHd(A.dst.a_h, 3 * sd + pb, rb, cb, plane_seed(k, 0 + A.salt), 0);
+    const RowAddr<T> bHd(A.dst.a_h, 3 * sd + pb, rb, cb, plane_seed(k, 1 + A.salt), sd);
+    const RowAddr<T> aFd(A.dst.a_h, 3 * sd + pb, rb, cb, plane_seed(k, 2 + A.salt), 2 * sd);
+    const RowAddr<T> bFd(A.dst.a_h, 3 * sd + pb, rb, cb, plane_seed(k, 3 + A.salt), 3 * sd);
     // rows beyond the zero border read its outermost (zero) row
     const int rmin = -kPadRows, rmax = cs.nx + kPadRows - 1;
 

@@ -240,6 +240,18 @@ __global__ __launch_bounds__(kRedThreads) void k_check_stable(Consts cs, const T
 
 inline int round_up8(int x) { return (x + 7) & ~7; }
 
+// The step tiles address a state set through one buffer descriptor: its four
+// planes must lie at one positive stride in the order a_h, b_h, a_f, b_f, and
+// the set must stay below 2 GiB (32-bit byte offsets).
+template <typename T>
+bool uniform_set(const Planes<T>& P)
+{
+    const char* a = reinterpret_cast<const char*>(P.a_h);
+    const std::ptrdiff_t st = reinterpret_cast<const char*>(P.b_h) - a;
+    return st > 0 && reinterpret_cast<const char*>(P.a_f) - a == 2 * st &&
+           reinterpret_cast<const char*>(P.b_f) - a == 3 * st && 4 * st < (std::ptrdiff_t{1} << 31);
+}
+
 // Whether the issue priority by progress (march_priority) pays for a launch of
 // `blocks` workgroups of `threads` threads of kernel `fn`: every workgroup is
 // resident at once (one round of wavefronts) and they fill at least a quarter
@@ -305,6 +317,7 @@ hipError_t launch_fused_step(const Consts& cs, const Shape& sh, Planes<T> src, P
                              const double* s_n, const double* g_m, double* acc_v,
                              double* acc_vc, const Ctl* ctl, int j_off, hipStream_t st)
 {
+    if (!uniform_set(src) || !uniform_set(dst)) return hipErrorInvalidValue;
     StepArgs<T> A;
     A.env = make_env(cs, sh, src, dst, s_n, g_m, acc_v, acc_vc, kWave - 2);
     A.ctl = ctl;
@@ -321,6 +334,7 @@ hipError_t launch_fused_step3(const Consts& cs, const Shape& sh, Planes<T> src, 
                               const double* s_n, const double* g_m, double* acc_v,
                               double* acc_vc, const Ctl* ctl, int j_off, hipStream_t st)
 {
+    if (!uniform_set(src) || !uniform_set(dst)) return hipErrorInvalidValue;
     StepArgs<T> A;
     // the wave's source coefficients cover its R harmonics plus 5 + 5 halo
     // harmonics, one per lane
@@ -341,6 +355,7 @@ hipError_t launch_fused_step2(const Consts& cs, const Shape& sh, Planes<T> src, 
                               const double* s_n, const double* g_m, double* acc_v,
                               double* acc_vc, const Ctl* ctl, int j_off, hipStream_t st)
 {
+    if (!uniform_set(src) || !uniform_set(dst)) return hipErrorInvalidValue;
     StepArgs<T> A;
     // the wave's source coefficients cover its R harmonics plus 3 + 3 halo
     // harmonics, one per lane

@@ -153,10 +153,10 @@ bte_status validate(const bte_grid* g, const bte_params* p)
     if (g->n_x > 16384 || g->n_y > (1 << 24)) return fail(BTE_EINVAL, "grid too large");
     if (p->flags != 0) return fail(BTE_EINVAL, "flags must be 0");
     {
-        // kernels address a plane with 32-bit byte offsets
+        // kernels address a set of four state planes with 32-bit byte offsets
         const Layout L = make_layout(*g, p->precision);
-        if (static_cast<double>(L.rows) * L.ld * L.elem >= 2147483648.0)
-            return fail(BTE_EINVAL, "grid too large: one state plane must stay below 2 GiB");
+        if (4.0 * static_cast<double>(L.plane_bytes) >= 2147483648.0)
+            return fail(BTE_EINVAL, "grid too large: a set of four state planes must stay below 2 GiB");
     }
     const double dphi = (g->phiy_max - g->phiy_min) / (g->n_y - 1);
     const double cfl = p->dt * std::fabs(p->B) / (2.0 * dphi);
