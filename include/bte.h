@@ -367,7 +367,9 @@ typedef struct bte_batch bte_batch;
    largest n_y -- one per workgroup, or one per instance for the wide
    schedule --, results), for the given tuning.  NULL tuning: FUSED2, 58
    harmonics per wave, 4 wavefronts per group, and the wide schedule unless
-   its slots would take more than 64 GiB (then the persistent one). */
+   its slots would take more than 64 GiB (then the persistent one).
+   BTE_EINVAL as bte_batch_create, including a largest grid whose set of four
+   state planes would reach 2 GiB. */
 bte_status bte_batch_workspace_bytes(const bte_batch_config* cfg, int32_t n,
                                      const bte_instance* inst, const bte_batch_tuning* tuning,
                                      size_t* bytes);

@@ -963,7 +963,10 @@ bte_status bte_batch_workspace_bytes(const bte_batch_config* cfg, int32_t n,
     if (st != BTE_OK) return st;
     if (!bytes) return bfail(BTE_EINVAL, "bytes must not be NULL");
     const bte_batch_tuning t = tuning ? *tuning : default_tuning_for(*cfg, n, ny_max);
-    *bytes = batch_layout(*cfg, n, ny_max, t).total;
+    const BatchLayout L = batch_layout(*cfg, n, ny_max, t);
+    if (4.0 * static_cast<double>(L.plane_bytes) >= 2147483648.0)
+        return bfail(BTE_EINVAL, "grid too large: a set of four state planes must stay below 2 GiB");
+    *bytes = L.total;
     return BTE_OK;
 }
 

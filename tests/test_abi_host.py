@@ -69,6 +69,23 @@ def test_invalid_arguments_rejected(grid_kw, param_kw, needle):
     assert needle in str(ei.value)
 
 
+def test_state_set_must_stay_below_2_gib():
+    """The step kernels address a set of four state planes with 32-bit byte
+    offsets: a grid whose four FP64 planes reach 2 GiB is rejected (one
+    plane alone is still far below it), the same grid in FP32 bulk and a
+    slightly smaller FP64 grid are accepted; the batch applies the same rule."""
+    big = _grid(n_x=1024, n_y=72700)
+    with pytest.raises(bte.BteError) as ei:
+        bte.bte_workspace_bytes(big, _params(B=0.0))
+    assert ei.value.status == bte.BTE_EINVAL and "four state planes" in str(ei.value)
+    assert bte.bte_workspace_bytes(big, _params(B=0.0, precision=bte.BTE_FP32_BULK)) > 0
+    assert bte.bte_workspace_bytes(_grid(n_x=1024, n_y=60000), _params(B=0.0)) > 0
+    with pytest.raises(bte.BteError) as ei:
+        bte.bte_batch_workspace_bytes(_cfg(n_x=1024, phiy_min=-10.0, phiy_max=10.0, dt=1e-4),
+                                      [_W(ny=72700, B=0.0)])
+    assert ei.value.status == bte.BTE_EINVAL and "four state planes" in str(ei.value)
+
+
 def test_omega_zero_allowed_without_ac_field():
     assert bte.bte_workspace_bytes(_grid(), _params(E_w=0.0, omega=0.0)) > 0
 
