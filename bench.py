@@ -681,11 +681,27 @@ def main():
                      "avg_launch_us": main_run["avg_launch_us"]},
         "status": main_run["status"],
     }
+    # observables over each run's timed window (the averaging window), and
+    # for every variant its difference from the FP64 run of the same workload
+    # and window: the error of each reported result against FP64
+    line["window"] = {"steps": main_run["window_steps"], "v_avg": main_run["v_avg"],
+                      "absorption": main_run["absorption"]}
     if variants:
-        line["variants"] = {k: {kk: v[kk] for kk in ("cell_steps_per_s", "us_per_step",
-                                                      "achieved_GBs", "avg_launch_us", "kernel",
-                                                      "tuning")}
-                            for k, v in variants.items()}
+        fp64_ref = {w.name: main_run} if precision == 0 else {}
+        for k, v in variants.items():
+            if k.endswith("_fp64"):
+                fp64_ref.setdefault(k[:-len("_fp64")], v)
+        line["variants"] = {}
+        for k, v in variants.items():
+            e = {kk: v[kk] for kk in ("cell_steps_per_s", "us_per_step", "achieved_GBs",
+                                      "avg_launch_us", "kernel", "tuning")}
+            e["window"] = {"steps": v["window_steps"], "v_avg": v["v_avg"],
+                           "absorption": v["absorption"]}
+            ref = next((r for name, r in fp64_ref.items() if k.startswith(name + "_")), None)
+            if ref is not None and ref is not v and ref["window_steps"] == v["window_steps"]:
+                e["vs_fp64"] = {"rel_v_avg": abs(v["v_avg"] - ref["v_avg"]) / abs(ref["v_avg"]),
+                                "abs_absorption": abs(v["absorption"] - ref["absorption"])}
+            line["variants"][k] = e
     if args.reconstruct > 0:
         line["reconstruct"] = reconstruct_bench(bte, torch, w, n_phix=args.reconstruct)
     if args.reconstruct_direct > 0:
