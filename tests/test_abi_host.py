@@ -139,6 +139,20 @@ def test_batch_workspace_bytes_and_validation():
     assert bte.bte_batch_workspace_bytes(_cfg(), inst, w) < bte.bte_batch_workspace_bytes(_cfg(), inst, t)
 
 
+def test_tuning_cache_key_classes():
+    """The binding's JSON tuning cache keys a pick the way the library's own
+    cache does: N_x, precision, the batch-size class (the smallest power of
+    two at or above min(n, 4096)) and the set of N_y values."""
+    cfg = _cfg()
+    k12 = bte.tuning_cache_key(cfg, [_W(ny=41)] * 11 + [_W(ny=81)])
+    assert k12 == f"nx16-p{cfg.precision}-n16-ny41,81"
+    assert bte.tuning_cache_key(cfg, [_W()] * 16).split("-")[2] == "n16"
+    assert bte.tuning_cache_key(cfg, [_W()] * 17).split("-")[2] == "n32"
+    assert bte.tuning_cache_key(cfg, [_W()] * 300).split("-")[2] == "n512"
+    assert bte.tuning_cache_key(cfg, [_W()] * 5000).split("-")[2] == "n4096"
+    assert bte.tuning_cache_key(cfg, [_W()]).split("-")[2] == "n1"
+
+
 def test_batch_tune_host_validation():
     """The sweep autotuner validates the batch before any device work."""
     for cfg, inst in [(_cfg(min_periods=1), [_W()]), (_cfg(), [_W(omega=0.0)]),
