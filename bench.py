@@ -408,6 +408,30 @@ def cpu_baseline(w, sample_steps):
                                      f"{secs1:.1f} s, 1 thread"}}
 
 
+def variant_report(main_run, variants, workload, precision):
+    """The bench line's `variants`: each timed run's rate and launch shape,
+    the observables of its timed window, and its difference from the FP64
+    run of the same workload and window (`vs_fp64`; the main run when it is
+    FP64, else the variant named <workload>_fp64).  Variant names are
+    <workload>_<rest>."""
+    fp64_ref = {workload: main_run} if precision == 0 else {}
+    for k, v in variants.items():
+        if k.endswith("_fp64"):
+            fp64_ref.setdefault(k[:-len("_fp64")], v)
+    out = {}
+    for k, v in variants.items():
+        e = {kk: v[kk] for kk in ("cell_steps_per_s", "us_per_step", "achieved_GBs",
+                                  "avg_launch_us", "kernel", "tuning")}
+        e["window"] = {"steps": v["window_steps"], "v_avg": v["v_avg"],
+                       "absorption": v["absorption"]}
+        ref = next((r for name, r in fp64_ref.items() if k.startswith(name + "_")), None)
+        if ref is not None and ref is not v and ref["window_steps"] == v["window_steps"]:
+            e["vs_fp64"] = {"rel_v_avg": abs(v["v_avg"] - ref["v_avg"]) / abs(ref["v_avg"]),
+                            "abs_absorption": abs(v["absorption"] - ref["absorption"])}
+        out[k] = e
+    return out
+
+
 def calibration_copy(torch, mib):
     """A plain device copy of known size (torch's copy: temporal 128-byte reads
     like the step kernels' row loads), five times, for scaling the HBM
@@ -687,21 +711,7 @@ def main():
     line["window"] = {"steps": main_run["window_steps"], "v_avg": main_run["v_avg"],
                       "absorption": main_run["absorption"]}
     if variants:
-        fp64_ref = {w.name: main_run} if precision == 0 else {}
-        for k, v in variants.items():
-            if k.endswith("_fp64"):
-                fp64_ref.setdefault(k[:-len("_fp64")], v)
-        line["variants"] = {}
-        for k, v in variants.items():
-            e = {kk: v[kk] for kk in ("cell_steps_per_s", "us_per_step", "achieved_GBs",
-                                      "avg_launch_us", "kernel", "tuning")}
-            e["window"] = {"steps": v["window_steps"], "v_avg": v["v_avg"],
-                           "absorption": v["absorption"]}
-            ref = next((r for name, r in fp64_ref.items() if k.startswith(name + "_")), None)
-            if ref is not None and ref is not v and ref["window_steps"] == v["window_steps"]:
-                e["vs_fp64"] = {"rel_v_avg": abs(v["v_avg"] - ref["v_avg"]) / abs(ref["v_avg"]),
-                                "abs_absorption": abs(v["absorption"] - ref["absorption"])}
-            line["variants"][k] = e
+        line["variants"] = variant_report(main_run, variants, w.name, precision)
     if args.reconstruct > 0:
         line["reconstruct"] = reconstruct_bench(bte, torch, w, n_phix=args.reconstruct)
     if args.reconstruct_direct > 0:
